@@ -1,0 +1,186 @@
+/*
+ * rk.h -- C ABI of the MI355X stage-parallel Radau IIA heat-equation library.
+ *
+ * Method (Munch, Dravins, Kronbichler, Neytcheva, arXiv:2209.06700):
+ *   the finite-element semi-discretisation  M y' + K y = g(t)  of the heat
+ *   equation u_t = Delta u + f on the unit cube with homogeneous Dirichlet
+ *   conditions, continuous Q_k elements (tensor products of 1D Lagrange
+ *   elements on Gauss-Lobatto points, (k+1)^3-point Gauss quadrature,
+ *   Sec. 5), advanced by the Q-stage Radau IIA method (Sec. 2).  Each step
+ *   solves the premultiplied stage system of eq. (irk:A),
+ *       (A_Q^-1 (x) M + tau I_Q (x) K) k = (A_Q^-1 (x) I)(gbar - e (x) K y_n),
+ *   with right-preconditioned flexible GMRES and the preconditioner of
+ *   eq. (irk:P), P^-1 = (S (x) I)(Lam (x) M + tau I (x) K)^-1 (S^-1 (x) I),
+ *   where A_Q^-1 = L U (Crout, unit-diagonal U) and L = S Lam S^-1.  Every
+ *   block lam_i M + tau K is approximated by one geometric-multigrid V-cycle
+ *   with a Chebyshev-Jacobi smoother and a Chebyshev coarse solve (Sec. 5).
+ *   Then y_{n+1} = y_n + tau sum_i b_i k_i (Sec. 1).
+ *
+ * Vector layout (every vector argument):
+ *   full grid of N = n_cells*degree + 1 nodes per direction, node (ix,iy,iz)
+ *   at offset ix + N*(iy + N*iz) (x fastest); Q-stage vectors are stage-major,
+ *   stage i at offset i*N^3.  Boundary nodes are part of the layout; on input
+ *   they are ignored (treated as 0), on output they are written as 0.
+ *   All vector pointers are DEVICE pointers owned by the caller.  The library
+ *   keeps no pointer to a caller vector after a call returns.
+ *
+ * Memory: the caller allocates one device workspace of rk_workspace_bytes()
+ *   bytes and passes it to rk_create(); the library never allocates device
+ *   memory itself.  The workspace must stay alive until rk_destroy().
+ *
+ * Streams: all device work of a context is enqueued on the HIP stream given
+ *   to rk_create() (NULL = the default stream).  rk_apply_operator(),
+ *   rk_vcycle() and rk_apply_preconditioner() are asynchronous; rk_create()
+ *   and rk_step() return after their device work has finished.
+ *
+ * Errors: every function returns RK_OK (0) or a negative code; no C++
+ *   exception crosses the ABI.  rk_last_error() returns a message for the
+ *   last failure of a context.  One context must not be used by two host
+ *   threads at the same time.
+ */
+#ifndef RK_H
+#define RK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define RK_OK          0
+#define RK_EINVAL     -1   /* bad argument: NULL pointer, size or enum out of range */
+#define RK_EWORKSPACE -2   /* workspace NULL or smaller than rk_workspace_bytes() */
+#define RK_EHIP       -3   /* a HIP runtime call failed; see rk_last_error() */
+#define RK_ENOCONV    -4   /* FGMRES hit max_iter; y is left unchanged */
+
+/* vector element types */
+#define RK_FP64 0
+#define RK_FP32 1
+
+/* preconditioner precision (rk_options.precision) */
+#define RK_PREC_FP64  0    /* V-cycles in fp64 */
+#define RK_PREC_MIXED 1    /* V-cycles, smoother, transfers in fp32 with fp32
+                              accumulation; FGMRES, orthogonalisation, residuals
+                              and the stage combination stay fp64 */
+
+/* block-solve mode (rk_options.mode) */
+#define RK_BATCHED   0     /* all Q blocks in every kernel launch (Sec. 3, batching) */
+#define RK_PER_STAGE 1     /* one block after the other (the paper's sequential IRK) */
+
+/* operator forms for rk_apply_operator */
+#define RK_OP_CALA   0     /* v = (A^-1 (x) M + tau I (x) K) u, Q stages, eq. (irk:A) */
+#define RK_OP_STAGE  1     /* v = (I (x) M + tau A (x) K) u,    Q stages (stage system, Sec. 2) */
+#define RK_OP_BLOCKS 2     /* v_i = (lam_i M + tau K) u_i,      Q stages, blocks of eq. (irk:P) */
+#define RK_OP_K      3     /* v = K u, one vector */
+#define RK_OP_M      4     /* v = M u, one vector */
+
+#define RK_MAX_Q      9
+#define RK_MAX_DEGREE 6
+#define RK_MAX_LEVELS 16
+
+typedef struct rk_ctx rk_ctx;
+
+/* Uniform mesh of [0,1]^3 with n_cells^3 hexahedra (n_cells = 2^L in Sec. 5;
+   any n_cells >= 1 here).  Multigrid levels halve n_cells while it is even. */
+typedef struct {
+    int32_t n_cells;
+} rk_mesh;
+
+typedef struct {
+    int32_t precision;          /* RK_PREC_FP64 | RK_PREC_MIXED                     */
+    int32_t mode;               /* RK_BATCHED | RK_PER_STAGE                        */
+    double  rtol;               /* FGMRES: stop when ||rhs - A k||_2 <= rtol ||rhs||_2 */
+    int32_t max_iter;           /* FGMRES iterations per step (all restarts)        */
+    int32_t restart;            /* Krylov basis length before a restart             */
+    int32_t cheb_degree;        /* smoother: V(nu,nu) with Chebyshev degree nu      */
+    int32_t coarse_cheb_degree; /* Chebyshev degree of the coarsest-level solve     */
+    double  cheb_range;         /* interval [upper/cheb_range, upper] for D^-1 A     */
+    double  eig_safety;         /* upper = eig_safety * estimated lambda_max         */
+    int32_t eig_iterations;     /* power iterations of that estimate                */
+    const double* eig_max;      /* host [n_levels]: explicit upper bounds (fine to
+                                   coarse), used as given; NULL = estimate at create */
+    int32_t timing;             /* 1: fill the per-component times of rk_stats     */
+} rk_options;
+
+typedef struct {
+    int32_t iterations;         /* FGMRES iterations of the step                    */
+    int32_t vcycles;            /* V-cycles (counted per block solve when per-stage,
+                                   per batched launch sequence when batched)         */
+    double  rel_residual;       /* true ||rhs - A k||_2 / ||rhs||_2 at the end      */
+    double  t_rhs, t_vmult, t_basis, t_blocks, t_rest;   /* seconds (timing = 1)     */
+} rk_stats;
+
+typedef struct {
+    int32_t N;                  /* nodes per direction, n_cells*degree + 1          */
+    int32_t n_cells, degree, Q, n_levels;
+    int32_t level_cells[RK_MAX_LEVELS];   /* cells per direction, fine to coarse   */
+    double  tau, h;
+    double  A[RK_MAX_Q * RK_MAX_Q], b[RK_MAX_Q], c[RK_MAX_Q];   /* Butcher tableau */
+    double  Ainv[RK_MAX_Q * RK_MAX_Q];
+    double  L[RK_MAX_Q * RK_MAX_Q];       /* Crout factor of A^-1 (lower)           */
+    double  S[RK_MAX_Q * RK_MAX_Q], Sinv[RK_MAX_Q * RK_MAX_Q];  /* L = S Lam S^-1  */
+    double  lambda[RK_MAX_Q];             /* Lam = diag(L)                          */
+    double  eig_max[RK_MAX_LEVELS];       /* Chebyshev upper bounds in use          */
+    double  nodes[RK_MAX_DEGREE + 1];     /* Gauss-Lobatto nodes on [0,1]           */
+} rk_info_t;
+
+/* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
+   max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
+   cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0. */
+void rk_default_options(rk_options* opt);
+
+/* Bytes of device workspace needed for the given mesh, degree (1..6),
+   Q (1..9) and options (opt may be NULL for the defaults). */
+int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt,
+                       size_t* bytes);
+
+/* Sets up a context: Radau IIA tableau (Sec. 2), A^-1 = L U, L = S Lam S^-1
+   (eq. irk:P), 1D element data, the level hierarchy, and the Chebyshev bounds
+   (estimated by power iteration on D^-1 A of every block unless
+   opt->eig_max is given; batched and per-stage runs share the largest bound
+   over the blocks of a level, as in the paper's batched runs).  d_workspace:
+   device memory of at least rk_workspace_bytes() bytes, 256-byte aligned.
+   hip_stream: a hipStream_t or NULL.  Blocks until set-up has finished. */
+int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_options* opt,
+              void* d_workspace, size_t workspace_bytes, void* hip_stream, rk_ctx** out);
+
+int rk_destroy(rk_ctx* ctx);
+
+/* Host copy of the context's sizes and Q x Q data. */
+int rk_info(const rk_ctx* ctx, rk_info_t* out);
+
+/* One Radau IIA step from t_n (Sec. 2).  d_y: fp64 [N^3], y_n on input,
+   y_{n+1} on output.  The source is g(t) = gamma(t) G: d_G is an fp64 [N^3]
+   load vector (int f phi_i; NULL means g = 0) and h_gamma a host array of Q
+   values gamma(t_n + c_i tau) (ignored when d_G is NULL).  h_stats may be NULL.
+   Returns RK_ENOCONV (y unchanged, stats filled) when max_iter is reached. */
+int rk_step(rk_ctx* ctx, double t_n, double* d_y, const double* d_G, const double* h_gamma,
+            rk_stats* h_stats);
+
+/* v = op(u) for one of the RK_OP_* forms, with dtype RK_FP64 or RK_FP32 for
+   both vectors.  Q-stage forms take [Q][N^3] vectors, RK_OP_K / RK_OP_M one
+   [N^3] vector.  u and v must not overlap.  Asynchronous. */
+int rk_apply_operator(rk_ctx* ctx, int form, int dtype, const void* d_u, void* d_v);
+
+/* x_i = one V-cycle for the block lam_i M + tau K applied to b_i, i = 1..Q,
+   on [Q][N^3] vectors.  dtype must be RK_FP32 for RK_PREC_MIXED contexts and
+   RK_FP64 otherwise.  Batched or per-stage as set in the options.  b and x
+   must not overlap.  Asynchronous. */
+int rk_vcycle(rk_ctx* ctx, int dtype, const void* d_b, void* d_x);
+
+/* z = P^-1 r (eq. irk:P) on fp64 [Q][N^3] vectors: basis change S^-1 (with
+   the cast to fp32 in mixed precision), the Q block V-cycles, basis change S.
+   r and z must not overlap.  Asynchronous. */
+int rk_apply_preconditioner(rk_ctx* ctx, const double* d_r, double* d_z);
+
+/* Message of the last failed call on ctx (or of the last failed rk_create
+   when ctx is NULL).  The pointer stays valid until the next call. */
+const char* rk_last_error(const rk_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RK_H */

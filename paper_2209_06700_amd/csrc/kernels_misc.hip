@@ -1,0 +1,566 @@
+// Streaming kernels: multigrid transfers, Chebyshev start, stage mixes
+// (basis changes, right-hand side), Krylov vector operations, reductions and
+// the stage combination.  All are bandwidth-bound grid-stride kernels with
+// coalesced x-fastest access.
+#include <hip/hip_runtime.h>
+
+#include "element_data.h"
+#include "rk_internal.h"
+
+namespace rk {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMP = RK_MAX_DEGREE + 1;
+
+// Element tables of every degree for kernels that index them at run time.
+struct AllTables {
+    double P[kMP][(2 * RK_MAX_DEGREE + 1) * kMP];   // prolongation, row-major (2k+1) x (k+1)
+    double dM[kMP][kMP];                            // 1D global mass diagonal by local index
+    double dA[kMP][kMP];                            // 1D global stiffness diagonal by local index
+};
+
+template <int K>
+constexpr void fill_tables(AllTables& t) {
+    constexpr auto d = elem::make<K>();
+    for (int f = 0; f <= 2 * K; ++f)
+        for (int c = 0; c <= K; ++c) t.P[K][f * (K + 1) + c] = d.P[f][c];
+    for (int r = 0; r < K; ++r) {
+        t.dM[K][r] = r == 0 ? d.M[0][0] + d.M[K][K] : d.M[r][r];
+        t.dA[K][r] = r == 0 ? d.A[0][0] + d.A[K][K] : d.A[r][r];
+    }
+}
+
+constexpr AllTables make_tables() {
+    AllTables t{};
+    fill_tables<1>(t);
+    fill_tables<2>(t);
+    fill_tables<3>(t);
+    fill_tables<4>(t);
+    fill_tables<5>(t);
+    fill_tables<6>(t);
+    return t;
+}
+
+__constant__ AllTables kTab = make_tables();
+
+template <typename T>
+struct Scal {
+    T alpha[RK_MAX_Q], beta[RK_MAX_Q];
+};
+
+template <typename T>
+Scal<T> to_scal(const StageScal& s) {
+    Scal<T> o;
+    for (int i = 0; i < RK_MAX_Q; ++i) { o.alpha[i] = T(s.alpha[i]); o.beta[i] = T(s.beta[i]); }
+    return o;
+}
+
+inline int grid_for(long long n, int cap = 8192) {
+    long long g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    return (int)(g > cap ? cap : g);
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid transfer, one 1D pass along `axis` of the tensor-product
+// prolongation P = P1 (x) P1 (x) P1 or its transpose (restriction).
+// P1 is the global 1D interpolation from the n-cell to the 2n-cell partition;
+// within coarse cell E the fine nodes 2Ek + j (j = 0..2k) take
+// sum_a Pe[j][a] x_c[Ek + a].
+// ---------------------------------------------------------------------------
+template <int K, typename T, bool RESTRICT, bool ADD>
+__global__ void __launch_bounds__(kBlock) transfer_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                        int ax, int dox, int doy, int doz,
+                                                        int dix, int diy, long long sin,
+                                                        long long sout, int nstage) {
+    constexpr int P = K + 1;
+    const double* Pe = kTab.P[K];
+    const long long per = (long long)dox * doy * doz;
+    const long long total = per * nstage;
+    const long long in_plane = (long long)dix * diy;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int s = (int)(idx / per);
+        long long r = idx - (long long)s * per;
+        const int oz = (int)(r / ((long long)dox * doy));
+        r -= (long long)oz * dox * doy;
+        const int oy = (int)(r / dox);
+        const int ox = (int)(r - (long long)oy * dox);
+        int o[3] = {ox, oy, oz};
+        const int dlen = ax == 0 ? dox : (ax == 1 ? doy : doz);   // output length on axis
+        const long long istep = ax == 0 ? 1 : (ax == 1 ? dix : in_plane);
+        const int pos = o[ax];
+        o[ax] = 0;
+        const long long ibase = (long long)s * sin + o[0] + (long long)o[1] * dix + (long long)o[2] * in_plane;
+        T val = T(0);
+        if (RESTRICT) {
+            // coarse node pos = E k + a; dlen = coarse length
+            const int nc = (dlen - 1) / K;
+            if (pos > 0 && pos < dlen - 1) {
+                const int E = pos / K, a = pos - E * K;
+                if (a == 0) {
+                    // vertex: column k of coarse cell E-1 and column 0 of cell E
+                    const long long f0 = 2LL * (E - 1) * K;
+#pragma unroll
+                    for (int j = 0; j <= 2 * K; ++j) val = fma(T(Pe[j * P + K]), in[ibase + (f0 + j) * istep], val);
+                    if (E < nc) {
+                        const long long f1 = 2LL * E * K;
+#pragma unroll
+                        for (int j = 1; j <= 2 * K; ++j) val = fma(T(Pe[j * P]), in[ibase + (f1 + j) * istep], val);
+                    }
+                } else {
+                    const long long f0 = 2LL * E * K;
+#pragma unroll
+                    for (int j = 0; j <= 2 * K; ++j) val = fma(T(Pe[j * P + a]), in[ibase + (f0 + j) * istep], val);
+                }
+            }
+        } else {
+            // fine node pos = 2 E k + j
+            if (pos > 0 && pos < dlen - 1) {
+                int E = pos / (2 * K), j = pos - E * 2 * K;
+                const long long c0 = (long long)E * K;
+#pragma unroll
+                for (int a = 0; a <= K; ++a) val = fma(T(Pe[j * P + a]), in[ibase + (c0 + a) * istep], val);
+            }
+        }
+        const long long oidx = (long long)s * sout + ox + (long long)oy * dox + (long long)oz * dox * doy;
+        if (ADD) out[oidx] += val;
+        else out[oidx] = val;
+    }
+}
+
+template <int K, typename T>
+hipError_t transfer_typed(const TransferLaunch& L) {
+    const long long total = (long long)L.dout[0] * L.dout[1] * L.dout[2] * L.nstage;
+    dim3 g(grid_for(total)), b(kBlock);
+    const T* in = static_cast<const T*>(L.in);
+    T* out = static_cast<T*>(L.out);
+    if (L.restrict_)
+        transfer_kernel<K, T, true, false><<<g, b, 0, L.stream>>>(in, out, L.axis, L.dout[0], L.dout[1], L.dout[2], L.din[0], L.din[1], L.sin, L.sout, L.nstage);
+    else if (L.add)
+        transfer_kernel<K, T, false, true><<<g, b, 0, L.stream>>>(in, out, L.axis, L.dout[0], L.dout[1], L.dout[2], L.din[0], L.din[1], L.sin, L.sout, L.nstage);
+    else
+        transfer_kernel<K, T, false, false><<<g, b, 0, L.stream>>>(in, out, L.axis, L.dout[0], L.dout[1], L.dout[2], L.din[0], L.din[1], L.sin, L.sout, L.nstage);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t transfer_k(const TransferLaunch& L) {
+    return L.dtype == RK_FP64 ? transfer_typed<K, double>(L) : transfer_typed<K, float>(L);
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi diagonal of the diagonal-mix record operator at node (x, y, z).
+// ---------------------------------------------------------------------------
+// Jacobi diagonal of the diagonal-mix operator (scales alpha, beta) at node
+// (x, y, z) of a degree-k grid.
+template <typename T>
+__device__ __forceinline__ T jacobi_diag(int k, T alpha, T beta, int x, int y, int z) {
+    const T mx = T(kTab.dM[k][x % k]), my = T(kTab.dM[k][y % k]), mz = T(kTab.dM[k][z % k]);
+    const T kx = T(kTab.dA[k][x % k]), ky = T(kTab.dA[k][y % k]), kz = T(kTab.dA[k][z % k]);
+    return fma(alpha, mx * my * mz, beta * (kx * my * mz + mx * ky * mz + mx * my * kz));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) cheb_first_kernel(Scal<T> sc, int k,
+                                                            const T* __restrict__ b, T* __restrict__ x,
+                                                            int n, int s0, int nstage, T cb) {
+    const int nK = n * k, N = nK + 1;
+    const long long N3 = (long long)N * N * N;
+    const long long total = N3 * nstage;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int sl = (int)(idx / N3);
+        const long long r = idx - (long long)sl * N3;
+        const int z = (int)(r / ((long long)N * N));
+        const int rr = (int)(r - (long long)z * N * N);
+        const int y = rr / N, xx = rr - y * N;
+        const int s = s0 + sl;
+        const long long off = (long long)s * N3 + r;
+        T val = T(0);
+        if (xx > 0 && xx < nK && y > 0 && y < nK && z > 0 && z < nK)
+            val = cb * b[off] / jacobi_diag(k, sc.alpha[s], sc.beta[s], xx, y, z);
+        x[off] = val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage mixes.
+// ---------------------------------------------------------------------------
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(kBlock) stage_mix_kernel(const Tin* __restrict__ in, Tout* __restrict__ out,
+                                                           const double* __restrict__ D, int qout,
+                                                           int qin, int N) {
+    const int nK = N - 1;
+    const long long N3 = (long long)N * N * N;
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N3;
+         r += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(r / ((long long)N * N));
+        const int rr = (int)(r - (long long)z * N * N);
+        const int y = rr / N, x = rr - y * N;
+        const bool inner = x > 0 && x < nK && y > 0 && y < nK && z > 0 && z < nK;
+        double u[RK_MAX_Q];
+#pragma unroll
+        for (int j = 0; j < RK_MAX_Q; ++j) u[j] = (j < qin && inner) ? (double)in[(long long)j * N3 + r] : 0.0;
+#pragma unroll
+        for (int i = 0; i < RK_MAX_Q; ++i) {
+            if (i >= qout) break;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < RK_MAX_Q; ++j)
+                if (j < qin) acc = fma(D[i * qin + j], u[j], acc);
+            out[(long long)i * N3 + r] = (Tout)acc;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) rhs_mix_kernel(const double* __restrict__ G, const double* __restrict__ w,
+                                                         double* __restrict__ out,
+                                                         const double* __restrict__ c1,
+                                                         const double* __restrict__ c2, int Q,
+                                                         long long n3) {
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n3;
+         r += (long long)gridDim.x * blockDim.x) {
+        const double g = G ? G[r] : 0.0;
+        const double wv = w[r];
+        for (int i = 0; i < Q; ++i) out[(long long)i * n3 + r] = fma(c1[i], g, c2[i] * wv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: wave64 shuffles, then LDS across the block's waves, then a
+// second fixed-order pass over the per-block partial sums (deterministic).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    return t;   // valid in thread 0
+}
+
+// dots of w against X_l, 8 vectors per sweep over w
+__global__ void __launch_bounds__(kBlock) dots_kernel(const double* __restrict__ X, int nvec, long long ld,
+                                                      const double* __restrict__ w, long long n,
+                                                      int self, double* __restrict__ part) {
+    __shared__ double sh[kBlock / 64];
+    const int nout = nvec + self;
+    const long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long step = (long long)gridDim.x * blockDim.x;
+    for (int l0 = 0; l0 < nout; l0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+        for (long long i = start; i < n; i += step) {
+            const double wi = w[i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int l = l0 + u;
+                if (l < nvec) acc[u] = fma(X[(long long)l * ld + i], wi, acc[u]);
+                else if (l == nvec && self) acc[u] = fma(wi, wi, acc[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (l0 + u >= nout) break;
+            const double t = block_sum(acc[u], sh);
+            if (threadIdx.x == 0) part[(long long)blockIdx.x * nout + l0 + u] = t;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) gs_update_kernel(const double* __restrict__ X, int nvec, long long ld,
+                                                           const double* __restrict__ h,
+                                                           double* __restrict__ w, long long n,
+                                                           double* __restrict__ norm_part) {
+    __shared__ double sh[kBlock / 64];
+    double nrm = 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double acc = w[i];
+        for (int l = 0; l < nvec; ++l) acc = fma(-h[l], X[(long long)l * ld + i], acc);
+        w[i] = acc;
+        nrm = fma(acc, acc, nrm);
+    }
+    if (norm_part) {
+        const double t = block_sum(nrm, sh);
+        if (threadIdx.x == 0) norm_part[blockIdx.x] = t;
+    }
+}
+
+__global__ void reduce_kernel(const double* __restrict__ part, int nblocks, int nout,
+                              double* __restrict__ out, int accumulate) {
+    __shared__ double sh[kBlock / 64];
+    const int l = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += part[(long long)b * nout + l];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[l] = accumulate ? out[l] + t : t;
+}
+
+__global__ void __launch_bounds__(kBlock) normalize_kernel(double* __restrict__ v, const double* __restrict__ w,
+                                                           const double* __restrict__ nrm2, long long n) {
+    const double inv = 1.0 / sqrt(*nrm2);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        v[i] = w[i] * inv;
+}
+
+template <typename TZ>
+__global__ void __launch_bounds__(kBlock) combine_kernel(double* __restrict__ kv, const TZ* __restrict__ Z, int nz,
+                                                         long long ld, const double* __restrict__ y,
+                                                         long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double acc = kv[i];
+        for (int j = 0; j < nz; ++j) acc = fma(y[j], (double)Z[(long long)j * ld + i], acc);
+        kv[i] = acc;
+    }
+}
+
+struct BVec {
+    double v[RK_MAX_Q];
+};
+
+__global__ void __launch_bounds__(kBlock) stage_combine_kernel(double* __restrict__ y, const double* __restrict__ kv,
+                                                               BVec b, double tau, int Q, long long n3) {
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n3;
+         r += (long long)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < RK_MAX_Q; ++i)
+            if (i < Q) acc = fma(b.v[i], kv[(long long)i * n3 + r], acc);
+        y[r] = fma(tau, acc, y[r]);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fill_kernel(T* __restrict__ x, long long n, T value) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] = value;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) copy_kernel(const T* __restrict__ src, T* __restrict__ dst, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Power iteration for the largest eigenvalue of D^-1 A per stage.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) power_partial_kernel(Scal<T> sc, int k,
+                                                               const T* __restrict__ v, const T* __restrict__ w,
+                                                               T* __restrict__ z, int n, int nstage,
+                                                               double* __restrict__ part) {
+    __shared__ double sh[kBlock / 64];
+    const int nK = n * k, N = nK + 1;
+    const long long N3 = (long long)N * N * N;
+    for (int s = 0; s < nstage; ++s) {
+        double vw = 0.0, vdv = 0.0, zz = 0.0;
+        for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N3;
+             r += (long long)gridDim.x * blockDim.x) {
+            const int zc = (int)(r / ((long long)N * N));
+            const int rr = (int)(r - (long long)zc * N * N);
+            const int y = rr / N, x = rr - y * N;
+            const long long off = (long long)s * N3 + r;
+            T zv = T(0);
+            if (x > 0 && x < nK && y > 0 && y < nK && zc > 0 && zc < nK) {
+                const double D = (double)jacobi_diag(k, sc.alpha[s], sc.beta[s], x, y, zc);
+                const double vv = (double)v[off], wv = (double)w[off];
+                vw = fma(vv, wv, vw);
+                vdv = fma(vv * D, vv, vdv);
+                zv = (T)(wv / D);
+                zz = fma((double)zv, (double)zv, zz);
+            }
+            z[off] = zv;
+        }
+        double t = block_sum(vw, sh);
+        if (threadIdx.x == 0) part[(long long)blockIdx.x * 3 * nstage + 3 * s + 0] = t;
+        t = block_sum(vdv, sh);
+        if (threadIdx.x == 0) part[(long long)blockIdx.x * 3 * nstage + 3 * s + 1] = t;
+        t = block_sum(zz, sh);
+        if (threadIdx.x == 0) part[(long long)blockIdx.x * 3 * nstage + 3 * s + 2] = t;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) power_normalize_kernel(const T* __restrict__ z, T* __restrict__ v,
+                                                                 const double* __restrict__ red, long long N3,
+                                                                 int nstage) {
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < N3 * nstage;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int s = (int)(idx / N3);
+        const double zz = red[3 * s + 2];
+        v[idx] = zz > 0.0 ? (T)((double)z[idx] / sqrt(zz)) : T(0);
+    }
+}
+
+__device__ __forceinline__ unsigned hash32(unsigned x) {
+    x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
+    return x;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) random_fill_kernel(T* __restrict__ x, int N, int nstage, unsigned seed) {
+    const long long N3 = (long long)N * N * N;
+    const int nK = N - 1;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < N3 * nstage;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long r = idx % N3;
+        const int z = (int)(r / ((long long)N * N));
+        const int rr = (int)(r - (long long)z * N * N);
+        const int y = rr / N, xx = rr - y * N;
+        T val = T(0);
+        if (xx > 0 && xx < nK && y > 0 && y < nK && z > 0 && z < nK) {
+            const unsigned h = hash32((unsigned)idx * 2654435761U ^ seed);
+            val = (T)((double)h * (2.0 / 4294967295.0) - 1.0);
+        }
+        x[idx] = val;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_transfer(const TransferLaunch& L) {
+    switch (L.k) {
+        case 1: return transfer_k<1>(L);
+        case 2: return transfer_k<2>(L);
+        case 3: return transfer_k<3>(L);
+        case 4: return transfer_k<4>(L);
+        case 5: return transfer_k<5>(L);
+        case 6: return transfer_k<6>(L);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* b, void* x, int n,
+                             int s0, int nstage, double cb, hipStream_t st) {
+    const long long N = (long long)n * k + 1;
+    dim3 g(grid_for(N * N * N * nstage)), blk(kBlock);
+    if (dtype == RK_FP64)
+        cheb_first_kernel<double><<<g, blk, 0, st>>>(to_scal<double>(sc), k, (const double*)b, (double*)x, n, s0, nstage, cb);
+    else
+        cheb_first_kernel<float><<<g, blk, 0, st>>>(to_scal<float>(sc), k, (const float*)b, (float*)x, n, s0, nstage, (float)cb);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* out, const double* D,
+                            int qout, int qin, int N, hipStream_t st) {
+    const long long N3 = (long long)N * N * N;
+    dim3 g(grid_for(N3)), b(kBlock);
+    if (dtype_in == RK_FP64 && dtype_out == RK_FP64)
+        stage_mix_kernel<double, double><<<g, b, 0, st>>>((const double*)in, (double*)out, D, qout, qin, N);
+    else if (dtype_in == RK_FP64 && dtype_out == RK_FP32)
+        stage_mix_kernel<double, float><<<g, b, 0, st>>>((const double*)in, (float*)out, D, qout, qin, N);
+    else if (dtype_in == RK_FP32 && dtype_out == RK_FP64)
+        stage_mix_kernel<float, double><<<g, b, 0, st>>>((const float*)in, (double*)out, D, qout, qin, N);
+    else
+        stage_mix_kernel<float, float><<<g, b, 0, st>>>((const float*)in, (float*)out, D, qout, qin, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_mix(const double* G, const double* w, double* out, const double* c1,
+                          const double* c2, int Q, long long n3, hipStream_t st) {
+    rhs_mix_kernel<<<grid_for(n3), kBlock, 0, st>>>(G, w, out, c1, c2, Q, n3);
+    return hipGetLastError();
+}
+
+hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w, long long n, int self,
+                       double* part, int nblocks, hipStream_t st) {
+    dots_kernel<<<nblocks, kBlock, 0, st>>>(X, nvec, ld, w, n, self, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, double* w,
+                            long long n, double* norm_part, int nblocks, hipStream_t st) {
+    gs_update_kernel<<<nblocks, kBlock, 0, st>>>(X, nvec, ld, h, w, n, norm_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* part, int nblocks, int nout, double* out, int accumulate,
+                         hipStream_t st) {
+    reduce_kernel<<<nout, kBlock, 0, st>>>(part, nblocks, nout, out, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(double* v, const double* w, const double* nrm2, long long n, hipStream_t st) {
+    normalize_kernel<<<grid_for(n), kBlock, 0, st>>>(v, w, nrm2, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(double* kv, int dtype_z, const void* Z, int nz, long long ld, const double* y,
+                          long long n, hipStream_t st) {
+    if (dtype_z == RK_FP64)
+        combine_kernel<double><<<grid_for(n), kBlock, 0, st>>>(kv, (const double*)Z, nz, ld, y, n);
+    else
+        combine_kernel<float><<<grid_for(n), kBlock, 0, st>>>(kv, (const float*)Z, nz, ld, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_combine(double* y, const double* kv, const double* b, double tau, int Q,
+                                long long n3, hipStream_t st) {
+    BVec bv;
+    for (int i = 0; i < RK_MAX_Q; ++i) bv.v[i] = i < Q ? b[i] : 0.0;
+    stage_combine_kernel<<<grid_for(n3), kBlock, 0, st>>>(y, kv, bv, tau, Q, n3);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int dtype, void* x, long long n, double value, hipStream_t st) {
+    if (dtype == RK_FP64) fill_kernel<double><<<grid_for(n), kBlock, 0, st>>>((double*)x, n, value);
+    else fill_kernel<float><<<grid_for(n), kBlock, 0, st>>>((float*)x, n, (float)value);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(int dtype, const void* src, void* dst, long long n, hipStream_t st) {
+    if (dtype == RK_FP64) copy_kernel<double><<<grid_for(n), kBlock, 0, st>>>((const double*)src, (double*)dst, n);
+    else copy_kernel<float><<<grid_for(n), kBlock, 0, st>>>((const float*)src, (float*)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_partial(int k, int dtype, const StageScal& sc, const void* v, const void* w, void* z,
+                                int n, int nstage, double* part, int nblocks, hipStream_t st) {
+    if (dtype == RK_FP64)
+        power_partial_kernel<double><<<nblocks, kBlock, 0, st>>>(to_scal<double>(sc), k, (const double*)v, (const double*)w, (double*)z, n, nstage, part);
+    else
+        power_partial_kernel<float><<<nblocks, kBlock, 0, st>>>(to_scal<float>(sc), k, (const float*)v, (const float*)w, (float*)z, n, nstage, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_normalize(int dtype, const void* z, void* v, const double* red, int N, int nstage,
+                                  hipStream_t st) {
+    const long long N3 = (long long)N * N * N;
+    if (dtype == RK_FP64)
+        power_normalize_kernel<double><<<grid_for(N3 * nstage), kBlock, 0, st>>>((const double*)z, (double*)v, red, N3, nstage);
+    else
+        power_normalize_kernel<float><<<grid_for(N3 * nstage), kBlock, 0, st>>>((const float*)z, (float*)v, red, N3, nstage);
+    return hipGetLastError();
+}
+
+hipError_t launch_random_fill(int dtype, void* x, int N, int nstage, unsigned seed, hipStream_t st) {
+    const long long N3 = (long long)N * N * N;
+    if (dtype == RK_FP64)
+        random_fill_kernel<double><<<grid_for(N3 * nstage), kBlock, 0, st>>>((double*)x, N, nstage, seed);
+    else
+        random_fill_kernel<float><<<grid_for(N3 * nstage), kBlock, 0, st>>>((float*)x, N, nstage, seed);
+    return hipGetLastError();
+}
+
+}  // namespace rk

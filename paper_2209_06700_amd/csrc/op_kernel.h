@@ -1,0 +1,414 @@
+// Matrix-free application of the stage operators on the uniform Q_k mesh.
+//
+// On the uniform hexahedral mesh the assembled mass and stiffness matrices are
+// sums of Kronecker products of 1D matrices (the element integrals separate
+// and every cell is a translate of the reference cube):
+//     M = m (x) m (x) m,   K = a (x) m (x) m + m (x) a (x) m + m (x) m (x) a,
+// where m and a are the 1D global mass and stiffness matrices, which are
+// assembled from the (k+1) x (k+1) element matrices Mhat, Khat.  The kernel
+// therefore evaluates the operator by sum factorisation over the whole grid:
+// one banded 1D product per direction and term, with no element gather/scatter
+// and no write conflicts (every output node is owned by exactly one thread).
+//
+// Work decomposition (one workgroup):
+//   * an x-y tile of TX x TY output nodes (element aligned) and a z-chunk of
+//     CZ elements; all Q stages of one tile are consecutive workgroups on one
+//     XCD so that the dense stage mix re-reads inputs from that XCD's L2;
+//   * the workgroup marches up the z-chunk one node plane at a time:
+//       1. the input plane tile plus a halo of k nodes below and 1 above in x
+//          and y is staged in LDS (zero outside the interior: Dirichlet);
+//       2. x-pass: every (row, x-element) item applies the 1D matrices to the
+//          2k+1 inputs it needs and writes k outputs to LDS;
+//       3. y-pass: every thread owns one x column and a y-pencil of k nodes
+//          (one element) and applies the 1D matrices along y from LDS;
+//       4. z: the plane's results are accumulated element by element into k+1
+//          per-thread registers per pencil node; when an element's top plane
+//          has been added, k output planes are complete and are written (with
+//          the epilogue: store, residual or Chebyshev update).
+//   The z-chunk re-reads the k planes of the element below it.
+//
+// Operator for output stage s (per-stage scalars in the kernel arguments,
+// 1D element matrices as compile-time constants):
+//   diagonal mix:  v_s = alpha_s Mref u_s + beta_s Kref u_s
+//   dense mix:     v_s = Mref (sum_j DM[s][j] u_j) + Kref (sum_j DK[s][j] u_j)
+// with Mref = Mhat (x) Mhat (x) Mhat etc. (cell size folded into the scales).
+// Sum factorisation used (per plane): with wM, wK the two mixed inputs,
+//   X1 = Mhat_x wM + Khat_x wK,  X2 = Mhat_x wK          (x-pass)
+//   S  = Mhat_y X1 + Khat_y X2,  T  = Mhat_y X2           (y-pass)
+//   v  = Mhat_z S + Khat_z T                              (z accumulation)
+// which expands to Mref wM + Kref wK.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "element_data.h"
+#include "rk_internal.h"
+
+namespace rk {
+namespace dev {
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1.
+template <typename F, int... I>
+__device__ __forceinline__ void cfor_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void cfor(F&& f) {
+    cfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Entry (A, B) of the 1D element mass (W = 0) or stiffness (W = 1) matrix.
+template <int K, int W, int A, int B>
+struct EC {
+    static constexpr double v = W == 0 ? elem::Table<K>::d.M[A][B] : elem::Table<K>::d.A[A][B];
+};
+
+// Diagonal of the 1D global matrix at a node with local index R (R = 0 is an
+// interior vertex shared by two cells).
+template <int K, int W, int R>
+struct DG {
+    static constexpr double v = R == 0 ? EC<K, W, 0, 0>::v + EC<K, W, K, K>::v : EC<K, W, R, R>::v;
+};
+
+template <int K>
+struct Tile {
+    static constexpr int CX = (32 / K) > 0 ? (32 / K) : 1;  // elements per tile in x
+    static constexpr int TX = CX * K;                       // owned nodes in x
+    static constexpr int CY = 8;                            // pencils per tile in y
+    static constexpr int TY = CY * K;                       // owned nodes in y
+    static constexpr int NT = TX * CY;                      // threads
+    static constexpr int RX = TX + K + 1;                   // staged input width
+    static constexpr int RY = TY + K + 1;                   // staged input height
+    static constexpr int XP = TX + 1;                       // padded LDS row of X1/X2
+    static constexpr int CZ = (32 / K) > 0 ? (32 / K) : 1;  // elements per z-chunk
+    static constexpr int TZ = CZ * K;
+};
+
+template <typename T>
+struct OpArgs {
+    const T* u;
+    T* v;
+    const T* b;
+    const T* xo;
+    long long stride;
+    int n, s0, nstage, qin;
+    int tiles_x, tiles_y, chunks_z, nwork, per_xcd;
+    int xo_zero;
+    T ca, cb;
+    T alpha[RK_MAX_Q], beta[RK_MAX_Q];            // diagonal mix, per stage
+    T DM[RK_MAX_Q * RK_MAX_Q], DK[RK_MAX_Q * RK_MAX_Q];   // dense mix
+};
+
+// out[a] = (E w)[a] for the k nodes eK..eK+k-1 of element e, where
+// w[0..2k] holds the inputs at nodes (e-1)k .. (e+1)k.  The vertex eK
+// collects row k of element e-1 and row 0 of element e.
+template <int K, int W, typename T>
+__device__ __forceinline__ void row_apply(const T* w, T* out) {
+    T o = T(EC<K, W, K, 0>::v) * w[0];
+    cfor<K - 1>([&](auto bm) {
+        constexpr int b = decltype(bm)::value + 1;
+        o = fma(T(EC<K, W, K, b>::v), w[b], o);
+    });
+    o = fma(T(EC<K, W, K, K>::v + EC<K, W, 0, 0>::v), w[K], o);
+    cfor<K>([&](auto bm) {
+        constexpr int b = decltype(bm)::value + 1;
+        o = fma(T(EC<K, W, 0, b>::v), w[K + b], o);
+    });
+    out[0] = o;
+    cfor<K - 1>([&](auto am) {
+        constexpr int a = decltype(am)::value + 1;
+        T q = T(EC<K, W, a, 0>::v) * w[K];
+        cfor<K>([&](auto bm) {
+            constexpr int b = decltype(bm)::value + 1;
+            q = fma(T(EC<K, W, a, b>::v), w[K + b], q);
+        });
+        out[a] = q;
+    });
+}
+
+// 1D diagonals at a runtime local index r in [0, K)
+template <int K, int W, typename T>
+__device__ __forceinline__ T diag_rt(int r) {
+    T d = T(DG<K, W, 0>::v);
+    cfor<K - 1>([&](auto rm) {
+        constexpr int rr = decltype(rm)::value + 1;
+        if (r == rr) d = T(DG<K, W, rr>::v);
+    });
+    return d;
+}
+
+template <int K, typename T, int MIX, int EPI>
+__global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
+    using TL = Tile<K>;
+    constexpr int P = K + 1;
+    constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, RX = TL::RX, RY = TL::RY;
+    constexpr int XP = TL::XP, CX = TL::CX, CZ = TL::CZ, TZ = TL::TZ;
+    constexpr int NU = MIX == MIX_DENSE ? 2 : 1;
+    __shared__ T sU[NU * RY * RX];
+    __shared__ T sX1[RY * XP];
+    __shared__ T sX2[RY * XP];
+
+    const int bid = blockIdx.x;
+    const int w = (bid & 7) * p.per_xcd + (bid >> 3);
+    if (w >= p.nwork) return;
+    int rem = w;
+    const int sl = rem % p.nstage;
+    rem /= p.nstage;
+    const int itx = rem % p.tiles_x;
+    rem /= p.tiles_x;
+    const int ity = rem % p.tiles_y;
+    const int icz = rem / p.tiles_y;
+    const int s = p.s0 + sl;
+
+    const int n = p.n, nK = n * K, N = nK + 1;
+    const long long NN = (long long)N * N;
+    const int X0 = itx * TX, Y0 = ity * TY, E0 = icz * CZ, Z0 = E0 * K;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, py = tid / TX;
+    const int gx = X0 + tx, gy0 = Y0 + py * K;
+    // vs may alias p.xo (in-place Chebyshev update), so it is not restrict.
+    T* vs = p.v + (long long)s * p.stride;
+
+    // Tiles that own only far-boundary nodes: write the zeros and leave.
+    if (X0 >= nK || Y0 >= nK || Z0 >= nK) {
+        const int z1 = min(Z0 + TZ, N);
+        if (gx < N)
+            for (int z = Z0; z < z1; ++z)
+#pragma unroll
+                for (int a = 0; a < K; ++a)
+                    if (gy0 + a < N) vs[z * NN + (long long)(gy0 + a) * N + gx] = T(0);
+        return;
+    }
+
+    T alpha = T(0), beta = T(0);
+    if (MIX == MIX_DIAG) {
+        alpha = p.alpha[s];
+        beta = p.beta[s];
+    }
+    const T* __restrict__ us = p.u + (long long)s * p.stride;
+
+    T acc[P][K];
+    T sv[K], tv[K];
+
+    // Load one node plane of the tile (+halo), x-pass, y-pass -> sv, tv.
+    auto plane = [&](int z) __attribute__((always_inline)) {
+        if (z <= 0 || z >= nK) {
+#pragma unroll
+            for (int a = 0; a < K; ++a) { sv[a] = T(0); tv[a] = T(0); }
+            return;
+        }
+        const long long zoff = (long long)z * NN;
+        for (int i = tid; i < RY * RX; i += NT) {
+            const int r = i / RX, c = i - r * RX;
+            const int xx = X0 - K + c, yy = Y0 - K + r;
+            T val = T(0), val2 = T(0);
+            if (xx > 0 && xx < nK && yy > 0 && yy < nK) {
+                const long long off = zoff + (long long)yy * N + xx;
+                if (MIX == MIX_DIAG) {
+                    val = us[off];
+                } else {
+                    for (int j = 0; j < p.qin; ++j) {
+                        const T uj = p.u[(long long)j * p.stride + off];
+                        val = fma(p.DM[s * RK_MAX_Q + j], uj, val);
+                        val2 = fma(p.DK[s * RK_MAX_Q + j], uj, val2);
+                    }
+                }
+            }
+            sU[i] = val;
+            if (MIX == MIX_DENSE) sU[RY * RX + i] = val2;
+        }
+        __syncthreads();
+        for (int it = tid; it < RY * CX; it += NT) {
+            const int cx = it / RY, r = it - cx * RY;
+            T wv[2 * K + 1], mx[K], kx[K];
+            const T* src = &sU[r * RX + cx * K];
+#pragma unroll
+            for (int j = 0; j <= 2 * K; ++j) wv[j] = src[j];
+            T* o1 = &sX1[r * XP + cx * K];
+            T* o2 = &sX2[r * XP + cx * K];
+            if (MIX == MIX_DIAG) {
+                row_apply<K, 0, T>(wv, mx);
+                row_apply<K, 1, T>(wv, kx);
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    o1[a] = fma(alpha, mx[a], beta * kx[a]);
+                    o2[a] = beta * mx[a];
+                }
+            } else {
+                T wk[2 * K + 1], mk[K];
+                const T* src2 = src + RY * RX;
+#pragma unroll
+                for (int j = 0; j <= 2 * K; ++j) wk[j] = src2[j];
+                row_apply<K, 0, T>(wv, mx);
+                row_apply<K, 1, T>(wk, kx);
+                row_apply<K, 0, T>(wk, mk);
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    o1[a] = mx[a] + kx[a];
+                    o2[a] = mk[a];
+                }
+            }
+        }
+        __syncthreads();
+        T w1[2 * K + 1], w2[2 * K + 1], m1[K], k2[K];
+#pragma unroll
+        for (int j = 0; j <= 2 * K; ++j) {
+            w1[j] = sX1[(py * K + j) * XP + tx];
+            w2[j] = sX2[(py * K + j) * XP + tx];
+        }
+        row_apply<K, 0, T>(w1, m1);
+        row_apply<K, 1, T>(w2, k2);
+        row_apply<K, 0, T>(w2, tv);
+#pragma unroll
+        for (int a = 0; a < K; ++a) sv[a] = m1[a] + k2[a];
+    };
+
+    // acc[c][a] += Mhat[c][B] sv[a] + Khat[c][B] tv[a]  (B compile-time)
+    auto zacc = [&](auto bm) __attribute__((always_inline)) {
+        constexpr int B = decltype(bm)::value;
+        cfor<P>([&](auto cm) {
+            constexpr int c = decltype(cm)::value;
+#pragma unroll
+            for (int a = 0; a < K; ++a)
+                acc[c][a] = fma(T(EC<K, 0, c, B>::v), sv[a], fma(T(EC<K, 1, c, B>::v), tv[a], acc[c][a]));
+        });
+    };
+    // acc[c][a] = Mhat[c][0] sv[a] + Khat[c][0] tv[a]
+    auto zinit = [&]() __attribute__((always_inline)) {
+        cfor<P>([&](auto cm) {
+            constexpr int c = decltype(cm)::value;
+#pragma unroll
+            for (int a = 0; a < K; ++a)
+                acc[c][a] = fma(T(EC<K, 0, c, 0>::v), sv[a], T(EC<K, 1, c, 0>::v) * tv[a]);
+        });
+    };
+
+    // Per-thread constants for the epilogue.
+    T dmx = T(0), dkx = T(0);
+    if (EPI == EPI_CHEB) {
+        const int rx = gx % K;
+        dmx = diag_rt<K, 0, T>(rx);
+        dkx = diag_rt<K, 1, T>(rx);
+    }
+    const T* __restrict__ bs = (EPI != EPI_STORE) ? p.b + (long long)s * p.stride : nullptr;
+    const T* xos = (EPI == EPI_CHEB && !p.xo_zero) ? p.xo + (long long)s * p.stride : nullptr;
+
+    auto flush = [&](int e) __attribute__((always_inline)) {
+        if (gx >= N) return;
+        cfor<K>([&](auto cm) {
+            constexpr int c = decltype(cm)::value;
+            const int z = e * K + c;
+            cfor<K>([&](auto am) {
+                constexpr int a = decltype(am)::value;
+                const int y = gy0 + a;
+                if (y < N) {
+                    const long long off = (long long)z * NN + (long long)y * N + gx;
+                    const bool bnd = gx == 0 || gx == nK || y == 0 || y == nK || z == 0;
+                    T out = T(0);
+                    if (!bnd) {
+                        const T av = acc[c][a];
+                        if (EPI == EPI_STORE) {
+                            out = av;
+                        } else if (EPI == EPI_RESID) {
+                            out = bs[off] - av;
+                        } else {
+                            constexpr T dmy = T(DG<K, 0, a>::v), dky = T(DG<K, 1, a>::v);
+                            constexpr T dmz = T(DG<K, 0, c>::v), dkz = T(DG<K, 1, c>::v);
+                            const T dM = dmx * (dmy * dmz);
+                            const T dK = dkx * (dmy * dmz) + dmx * (dky * dmz + dmy * dkz);
+                            const T D = fma(alpha, dM, beta * dK);
+                            const T x = us[off];
+                            const T xo = xos ? xos[off] : T(0);
+                            out = x + p.ca * (x - xo) + p.cb * (bs[off] - av) / D;
+                        }
+                    }
+                    vs[off] = out;
+                }
+            });
+        });
+    };
+
+    const int E1 = min(E0 + CZ, n);
+    const int ebeg = E0 > 0 ? E0 - 1 : 0;
+    plane(ebeg * K);
+    zinit();
+    for (int e = ebeg; e < E1; ++e) {
+#pragma unroll 1
+        for (int b = 1; b <= K; ++b) {
+            plane(e * K + b);
+            cfor<K>([&](auto bm) {
+                constexpr int B = decltype(bm)::value + 1;
+                if (b == B) zacc(std::integral_constant<int, B>{});
+            });
+        }
+        if (e >= E0) flush(e);
+        // The top plane of element e is the bottom plane of element e+1.
+        T carry[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) carry[a] = acc[K][a];
+        zinit();
+#pragma unroll
+        for (int a = 0; a < K; ++a) acc[0][a] += carry[a];
+    }
+    // The chunk that contains the top boundary plane writes it.
+    if (E0 + CZ > n && gx < N) {
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+            if (gy0 + a < N) vs[(long long)nK * NN + (long long)(gy0 + a) * N + gx] = T(0);
+    }
+}
+
+template <int K, typename T>
+hipError_t launch_op_typed(const OpLaunch& L) {
+    using TL = Tile<K>;
+    OpArgs<T> p;
+    p.u = static_cast<const T*>(L.u);
+    p.v = static_cast<T*>(L.v);
+    p.b = static_cast<const T*>(L.b);
+    p.xo = static_cast<const T*>(L.xo);
+    p.stride = L.stride;
+    p.n = L.n;
+    p.s0 = L.s0;
+    p.nstage = L.nstage;
+    p.qin = L.qin;
+    const int N = L.n * K + 1;
+    p.tiles_x = (N + TL::TX - 1) / TL::TX;
+    p.tiles_y = (N + TL::TY - 1) / TL::TY;
+    p.chunks_z = (N + TL::TZ - 1) / TL::TZ;
+    p.nwork = p.tiles_x * p.tiles_y * p.chunks_z * L.nstage;
+    p.per_xcd = (p.nwork + 7) / 8;
+    p.xo_zero = L.xo == nullptr;
+    p.ca = T(L.ca);
+    p.cb = T(L.cb);
+    for (int i = 0; i < RK_MAX_Q; ++i) {
+        p.alpha[i] = T(L.alpha[i]);
+        p.beta[i] = T(L.beta[i]);
+    }
+    for (int i = 0; i < RK_MAX_Q * RK_MAX_Q; ++i) {
+        p.DM[i] = T(L.DM[i]);
+        p.DK[i] = T(L.DK[i]);
+    }
+    dim3 grid(8 * p.per_xcd), block(TL::NT);
+#define RK_OP_CASE(MX, EP)                                                      \
+    if (L.mix == MX && L.epi == EP) {                                           \
+        op_kernel<K, T, MX, EP><<<grid, block, 0, L.stream>>>(p);               \
+        return hipGetLastError();                                               \
+    }
+    RK_OP_CASE(MIX_DIAG, EPI_STORE)
+    RK_OP_CASE(MIX_DIAG, EPI_RESID)
+    RK_OP_CASE(MIX_DIAG, EPI_CHEB)
+    RK_OP_CASE(MIX_DENSE, EPI_STORE)
+    RK_OP_CASE(MIX_DENSE, EPI_RESID)
+#undef RK_OP_CASE
+    return hipErrorInvalidValue;
+}
+
+template <int K>
+hipError_t launch_op_k(const OpLaunch& L) {
+    return L.dtype == RK_FP64 ? launch_op_typed<K, double>(L) : launch_op_typed<K, float>(L);
+}
+
+}  // namespace dev
+}  // namespace rk

@@ -1,0 +1,6 @@
+// Instantiation of the matrix-free operator kernels for degree 1.
+#include "op_kernel.h"
+
+namespace rk {
+hipError_t launch_op_k1(const OpLaunch& L) { return dev::launch_op_k<1>(L); }
+}  // namespace rk

@@ -1,0 +1,6 @@
+// Instantiation of the matrix-free operator kernels for degree 6.
+#include "op_kernel.h"
+
+namespace rk {
+hipError_t launch_op_k6(const OpLaunch& L) { return dev::launch_op_k<6>(L); }
+}  // namespace rk

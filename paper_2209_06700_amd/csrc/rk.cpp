@@ -1,0 +1,784 @@
+// Host driver of the C ABI declared in include/rk.h.
+//
+// The context owns no device allocation: every device buffer is carved out of
+// the caller's workspace.  All device work is enqueued on the context stream;
+// the only device-to-host transfers in a time step are the Arnoldi scalars of
+// each FGMRES iteration (one small copy and one stream synchronisation).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rk_internal.h"
+
+using namespace rk;
+
+namespace rk {
+hipError_t launch_op_k1(const OpLaunch&);
+hipError_t launch_op_k2(const OpLaunch&);
+hipError_t launch_op_k3(const OpLaunch&);
+hipError_t launch_op_k4(const OpLaunch&);
+hipError_t launch_op_k5(const OpLaunch&);
+hipError_t launch_op_k6(const OpLaunch&);
+
+hipError_t launch_op(const OpLaunch& L) {
+    switch (L.k) {
+        case 1: return launch_op_k1(L);
+        case 2: return launch_op_k2(L);
+        case 3: return launch_op_k3(L);
+        case 4: return launch_op_k4(L);
+        case 5: return launch_op_k5(L);
+        case 6: return launch_op_k6(L);
+        default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace rk
+
+namespace {
+
+constexpr int kRedBlocks = 1024;     // blocks of the reduction kernels
+constexpr size_t kAlign = 256;
+
+enum Form { F_CALA = 0, F_STAGE = 1, F_BLOCKS = 2, F_K = 3, F_M = 4, F_NFORMS = 5 };
+
+// Mixing coefficients of one operator form (cell size folded in).
+struct Coeffs {
+    double alpha[RK_MAX_Q] = {}, beta[RK_MAX_Q] = {};
+    double DM[RK_MAX_Q * RK_MAX_Q] = {}, DK[RK_MAX_Q * RK_MAX_Q] = {};
+    bool dense = false;
+};
+
+struct Level {
+    int n = 0, N = 0;
+    long long N3 = 0;
+    double h = 0.0;
+    void* b = nullptr;      // [Q][N3], preconditioner dtype
+    void* x = nullptr;
+    void* y = nullptr;
+    Coeffs blk;             // block operators lam_i M + tau K on this level
+    double eig_max = 1.0;
+};
+
+struct Event {
+    hipEvent_t a, b;
+    int comp;
+};
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    size_t cap;
+    void* take(size_t bytes) {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        void* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+size_t dsize(int dtype) { return dtype == RK_FP64 ? 8 : 4; }
+
+std::string g_create_error;
+
+}  // namespace
+
+struct rk_ctx {
+    int n = 0, k = 0, Q = 0, N = 0;
+    long long N3 = 0;
+    double tau = 0.0, h = 0.0;
+    rk_options opt{};
+    std::vector<double> eig_user;
+    Tableau tab{};
+    Element1D el{};
+    hipStream_t stream = nullptr;
+    int pc = RK_FP64;              // preconditioner dtype
+    std::vector<Level> lv;
+    Coeffs form[F_NFORMS];         // fine-level operator coefficients
+    void* tmp1 = nullptr;
+    void* tmp2 = nullptr;
+    double* V = nullptr;           // (restart+1) x Q N3
+    double* Z = nullptr;           // restart x Q N3
+    double* w = nullptr;           // Q N3
+    double* kv = nullptr;          // Q N3
+    double* rhs = nullptr;         // Q N3
+    double* r = nullptr;           // Q N3
+    double* Ky = nullptr;          // N3
+    double* part = nullptr;        // kRedBlocks x (restart + 8)
+    double* scal = nullptr;        // restart + 16 device scalars
+    double* scal2 = nullptr;       // restart + 16
+    double* ycoef = nullptr;       // restart
+    double* mix = nullptr;         // 4 x 81: Sinv, S, c1, c2
+    std::vector<double> host_scal;
+    std::vector<Event> events;
+    std::vector<Event> event_pool;
+    size_t pool_used = 0;
+    std::string err;
+};
+
+namespace {
+
+int fail(rk_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, RK_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+std::vector<int> level_cells(int n) {
+    std::vector<int> out{n};
+    while (out.back() % 2 == 0 && (int)out.size() < RK_MAX_LEVELS) out.push_back(out.back() / 2);
+    return out;
+}
+
+bool valid_options(const rk_options& o, std::string& msg) {
+    if (o.precision != RK_PREC_FP64 && o.precision != RK_PREC_MIXED) { msg = "bad precision"; return false; }
+    if (o.mode != RK_BATCHED && o.mode != RK_PER_STAGE) { msg = "bad mode"; return false; }
+    if (!(o.rtol > 0.0) || o.max_iter < 1 || o.restart < 1 || o.restart > 256) { msg = "bad FGMRES settings"; return false; }
+    if (o.cheb_degree < 1 || o.coarse_cheb_degree < 1 || o.cheb_degree > 64 || o.coarse_cheb_degree > 64) {
+        msg = "bad Chebyshev degree"; return false;
+    }
+    if (!(o.cheb_range > 1.0) || !(o.eig_safety > 0.0) || o.eig_iterations < 1) { msg = "bad Chebyshev interval settings"; return false; }
+    return true;
+}
+
+// Coefficients of an operator form on a grid with cell size h:
+//   CALA:   v_s = h^3 sum_j Ainv_sj Mref u_j + tau h Kref u_s      (eq. irk:A)
+//   STAGE:  v_s = h^3 Mref u_s + tau h sum_j A_sj Kref u_j         (stage system)
+//   BLOCKS: v_s = lam_s h^3 Mref u_s + tau h Kref u_s              (eq. irk:P blocks)
+//   K, M:   one vector.
+Coeffs make_coeffs(const rk_ctx& c, double h, int form) {
+    const int Q = c.Q;
+    Coeffs r;
+    const double h3 = h * h * h;
+    for (int s = 0; s < RK_MAX_Q; ++s) {
+        if (form == F_BLOCKS && s < Q) { r.alpha[s] = c.tab.lam[s] * h3; r.beta[s] = c.tau * h; }
+        if (form == F_K) { r.alpha[s] = 0.0; r.beta[s] = h; }
+        if (form == F_M) { r.alpha[s] = h3; r.beta[s] = 0.0; }
+    }
+    r.dense = form == F_CALA || form == F_STAGE;
+    for (int s = 0; s < Q; ++s)
+        for (int j = 0; j < Q; ++j) {
+            double dm = 0.0, dk = 0.0;
+            if (form == F_CALA) { dm = h3 * c.tab.Ainv[s * Q + j]; dk = (s == j) ? c.tau * h : 0.0; }
+            if (form == F_STAGE) { dm = (s == j) ? h3 : 0.0; dk = c.tau * h * c.tab.A[s * Q + j]; }
+            r.DM[s * RK_MAX_Q + j] = dm;
+            r.DK[s * RK_MAX_Q + j] = dk;
+        }
+    return r;
+}
+
+StageScal to_stage_scal(const Coeffs& cf) {
+    StageScal s;
+    for (int i = 0; i < RK_MAX_Q; ++i) { s.alpha[i] = cf.alpha[i]; s.beta[i] = cf.beta[i]; }
+    return s;
+}
+
+// Carve the workspace (base == nullptr: size query).
+size_t carve(rk_ctx& c, char* base) {
+    Carver cv{base, 0, 0};
+    const int Q = c.Q, k = c.k;
+    const size_t pcs = dsize(c.pc);
+    (void)k;
+    for (auto& L : c.lv) {
+        L.b = cv.take(pcs * Q * L.N3);
+        L.x = cv.take(pcs * Q * L.N3);
+        L.y = cv.take(pcs * Q * L.N3);
+    }
+    size_t tmp = 1;
+    for (size_t l = 0; l + 1 < c.lv.size(); ++l)
+        tmp = std::max(tmp, (size_t)c.lv[l + 1].N * c.lv[l].N * c.lv[l].N);
+    c.tmp1 = cv.take(pcs * Q * tmp);
+    c.tmp2 = cv.take(pcs * Q * tmp);
+    const long long qn = (long long)Q * c.N3;
+    const int m = c.opt.restart;
+    c.V = (double*)cv.take(8 * (size_t)(m + 1) * qn);
+    c.Z = (double*)cv.take(8 * (size_t)m * qn);
+    c.w = (double*)cv.take(8 * qn);
+    c.kv = (double*)cv.take(8 * qn);
+    c.rhs = (double*)cv.take(8 * qn);
+    c.r = (double*)cv.take(8 * qn);
+    c.Ky = (double*)cv.take(8 * c.N3);
+    const size_t nscal = std::max(m + 16, 3 * RK_MAX_Q + 1);
+    c.part = (double*)cv.take(8 * (size_t)kRedBlocks * nscal);
+    c.scal = (double*)cv.take(8 * nscal);
+    c.scal2 = (double*)cv.take(8 * nscal);
+    c.ycoef = (double*)cv.take(8 * (size_t)(m + 16));
+    c.mix = (double*)cv.take(8 * 4 * 81);
+    return cv.off + kAlign;
+}
+
+int setup_sizes(rk_ctx& c, const rk_mesh* mesh, int degree, int Q, const rk_options* opt) {
+    if (!mesh || mesh->n_cells < 1 || degree < 1 || degree > RK_MAX_DEGREE || Q < 1 || Q > RK_MAX_Q)
+        return fail(nullptr, RK_EINVAL, "mesh, degree (1..6) or Q (1..9) out of range");
+    if (opt) c.opt = *opt;
+    else rk_default_options(&c.opt);
+    std::string msg;
+    if (!valid_options(c.opt, msg)) return fail(nullptr, RK_EINVAL, msg);
+    c.n = mesh->n_cells;
+    c.k = degree;
+    c.Q = Q;
+    c.N = c.n * c.k + 1;
+    c.N3 = (long long)c.N * c.N * c.N;
+    c.h = 1.0 / c.n;
+    c.pc = c.opt.precision == RK_PREC_MIXED ? RK_FP32 : RK_FP64;
+    c.lv.clear();
+    for (int m : level_cells(c.n)) {
+        Level L;
+        L.n = m;
+        L.N = m * c.k + 1;
+        L.N3 = (long long)L.N * L.N * L.N;
+        L.h = 1.0 / m;
+        c.lv.push_back(L);
+    }
+    return RK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Component timing with events (only when opt.timing is set).
+// ---------------------------------------------------------------------------
+enum Comp { C_RHS = 0, C_VMULT, C_BASIS, C_BLOCKS, C_REST, C_N };
+
+struct Timer {
+    rk_ctx* c;
+    int comp;
+    Event* ev = nullptr;
+    Timer(rk_ctx* ctx, int cp) : c(ctx), comp(cp) {
+        if (!c->opt.timing) return;
+        if (c->pool_used == c->event_pool.size()) {
+            Event e{};
+            (void)hipEventCreate(&e.a);
+            (void)hipEventCreate(&e.b);
+            c->event_pool.push_back(e);
+        }
+        ev = &c->event_pool[c->pool_used++];
+        ev->comp = comp;
+        (void)hipEventRecord(ev->a, c->stream);
+    }
+    ~Timer() {
+        if (ev) (void)hipEventRecord(ev->b, c->stream);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Operators and the V-cycle.
+// ---------------------------------------------------------------------------
+int op(rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, void* v,
+       const void* b, const void* xo, int n, int s0, int ns, int qin, double ca, double cb) {
+    OpLaunch L;
+    L.k = k; L.dtype = dtype; L.mix = cf.dense ? MIX_DENSE : MIX_DIAG; L.epi = epi;
+    L.u = u; L.v = v; L.b = b; L.xo = xo;
+    for (int i = 0; i < RK_MAX_Q; ++i) { L.alpha[i] = cf.alpha[i]; L.beta[i] = cf.beta[i]; }
+    for (int i = 0; i < RK_MAX_Q * RK_MAX_Q; ++i) { L.DM[i] = cf.DM[i]; L.DK[i] = cf.DK[i]; }
+    const long long N = (long long)n * k + 1;
+    L.stride = N * N * N;
+    L.n = n; L.s0 = s0; L.nstage = ns; L.qin = qin; L.ca = ca; L.cb = cb;
+    L.stream = c->stream;
+    HIPCHK(c, launch_op(L));
+    return RK_OK;
+}
+
+struct ChebCoef {
+    double theta, delta, sigma;
+};
+
+ChebCoef cheb_coef(double up, double range) {
+    const double lo = up / range;
+    ChebCoef cc;
+    cc.theta = 0.5 * (up + lo);
+    cc.delta = 0.5 * (up - lo);
+    cc.sigma = cc.theta / cc.delta;
+    return cc;
+}
+
+// Chebyshev iteration of `degree` steps on level l for stages [s0, s0+ns).
+// first/second: stage-0 base pointers of the two iterate buffers.  If
+// zero_start, x_0 = 0; otherwise x_0 is in `first`.  Returns the buffer that
+// holds the result through *res.
+int chebyshev(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, void* second,
+              bool zero_start, int degree, void** res) {
+    Level& L = c->lv[l];
+    const ChebCoef cc = cheb_coef(L.eig_max, c->opt.cheb_range);
+    const int k = c->k, dt = c->pc;
+    void* cur;     // x_j
+    void* prev;    // x_{j-1} (or null when x_{j-1} = 0)
+    void* other;
+    if (zero_start) {
+        HIPCHK(c, launch_cheb_first(k, dt, to_stage_scal(L.blk), b, first, L.n, s0, ns, 1.0 / cc.theta, c->stream));
+        cur = first; prev = nullptr; other = second;
+    } else {
+        int rc = op(c, k, dt, EPI_CHEB, L.blk, first, second, b, nullptr, L.n, s0, ns, 1, 0.0, 1.0 / cc.theta);
+        if (rc) return rc;
+        cur = second; prev = first; other = first;
+    }
+    double rho = 1.0 / cc.sigma;
+    for (int j = 1; j < degree; ++j) {
+        const double rho_new = 1.0 / (2.0 * cc.sigma - rho);
+        const double ca = rho_new * rho, cb = 2.0 * rho_new / cc.delta;
+        // x_{j+1} overwrites the buffer of x_{j-1} (or the free buffer)
+        void* out = prev ? prev : other;
+        int rc = op(c, k, dt, EPI_CHEB, L.blk, cur, out, b, prev, L.n, s0, ns, 1, ca, cb);
+        if (rc) return rc;
+        prev = cur;
+        cur = out;
+        rho = rho_new;
+    }
+    *res = cur;
+    return RK_OK;
+}
+
+int restrict_to(rk_ctx* c, int l, int s0, int ns, const void* fine) {
+    Level& F = c->lv[l];
+    Level& C = c->lv[l + 1];
+    const size_t es = dsize(c->pc);
+    const int nf = F.N, nc = C.N;
+    TransferLaunch T;
+    T.k = c->k; T.dtype = c->pc; T.restrict_ = true; T.nstage = ns; T.stream = c->stream;
+    // x: (nf,nf,nf) -> (nc,nf,nf)
+    T.axis = 0; T.in = (const char*)fine + es * s0 * F.N3; T.out = c->tmp1;
+    T.din[0] = nf; T.din[1] = nf; T.din[2] = nf; T.dout[0] = nc; T.dout[1] = nf; T.dout[2] = nf;
+    T.sin = F.N3; T.sout = (long long)nc * nf * nf;
+    HIPCHK(c, launch_transfer(T));
+    // y: (nc,nf,nf) -> (nc,nc,nf)
+    T.axis = 1; T.in = c->tmp1; T.out = c->tmp2;
+    T.din[0] = nc; T.din[1] = nf; T.din[2] = nf; T.dout[0] = nc; T.dout[1] = nc; T.dout[2] = nf;
+    T.sin = (long long)nc * nf * nf; T.sout = (long long)nc * nc * nf;
+    HIPCHK(c, launch_transfer(T));
+    // z: (nc,nc,nf) -> (nc,nc,nc)
+    T.axis = 2; T.in = c->tmp2; T.out = (char*)C.b + es * s0 * C.N3;
+    T.din[0] = nc; T.din[1] = nc; T.din[2] = nf; T.dout[0] = nc; T.dout[1] = nc; T.dout[2] = nc;
+    T.sin = (long long)nc * nc * nf; T.sout = C.N3;
+    HIPCHK(c, launch_transfer(T));
+    return RK_OK;
+}
+
+int prolong_add(rk_ctx* c, int l, int s0, int ns, const void* coarse, void* fine) {
+    Level& F = c->lv[l];
+    Level& C = c->lv[l + 1];
+    const size_t es = dsize(c->pc);
+    const int nf = F.N, nc = C.N;
+    TransferLaunch T;
+    T.k = c->k; T.dtype = c->pc; T.restrict_ = false; T.nstage = ns; T.stream = c->stream;
+    // z: (nc,nc,nc) -> (nc,nc,nf)
+    T.axis = 2; T.add = false; T.in = (const char*)coarse + es * s0 * C.N3; T.out = c->tmp1;
+    T.din[0] = nc; T.din[1] = nc; T.din[2] = nc; T.dout[0] = nc; T.dout[1] = nc; T.dout[2] = nf;
+    T.sin = C.N3; T.sout = (long long)nc * nc * nf;
+    HIPCHK(c, launch_transfer(T));
+    // y: (nc,nc,nf) -> (nc,nf,nf)
+    T.axis = 1; T.in = c->tmp1; T.out = c->tmp2;
+    T.din[0] = nc; T.din[1] = nc; T.din[2] = nf; T.dout[0] = nc; T.dout[1] = nf; T.dout[2] = nf;
+    T.sin = (long long)nc * nc * nf; T.sout = (long long)nc * nf * nf;
+    HIPCHK(c, launch_transfer(T));
+    // x: (nc,nf,nf) -> (nf,nf,nf), added
+    T.axis = 0; T.add = true; T.in = c->tmp2; T.out = (char*)fine + es * s0 * F.N3;
+    T.din[0] = nc; T.din[1] = nf; T.din[2] = nf; T.dout[0] = nf; T.dout[1] = nf; T.dout[2] = nf;
+    T.sin = (long long)nc * nf * nf; T.sout = F.N3;
+    HIPCHK(c, launch_transfer(T));
+    return RK_OK;
+}
+
+// One V-cycle on level l for stages [s0, s0+ns): b -> result, using the two
+// buffers first/second.  For l < last the result always lands in `second`;
+// on the coarsest level in `first` for an odd coarse degree, else `second`.
+int vcycle_level(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, void* second, void** res) {
+    const int last = (int)c->lv.size() - 1;
+    if (l == last) return chebyshev(c, l, s0, ns, b, first, second, true, c->opt.coarse_cheb_degree, res);
+    Level& L = c->lv[l];
+    void* pre = nullptr;
+    int rc = chebyshev(c, l, s0, ns, b, first, second, true, c->opt.cheb_degree, &pre);
+    if (rc) return rc;
+    void* spare = (pre == first) ? second : first;
+    // residual into the spare buffer
+    rc = op(c, c->k, c->pc, EPI_RESID, L.blk, pre, spare, b, nullptr, L.n, s0, ns, 1, 0, 0);
+    if (rc) return rc;
+    rc = restrict_to(c, l, s0, ns, spare);
+    if (rc) return rc;
+    Level& C = c->lv[l + 1];
+    void* cres = nullptr;
+    rc = vcycle_level(c, l + 1, s0, ns, C.b, C.x, C.y, &cres);
+    if (rc) return rc;
+    rc = prolong_add(c, l, s0, ns, cres, pre);
+    if (rc) return rc;
+    void* post = nullptr;
+    rc = chebyshev(c, l, s0, ns, b, pre, spare, false, c->opt.cheb_degree, &post);
+    if (rc) return rc;
+    *res = post;
+    return RK_OK;
+}
+
+// V-cycles for all Q blocks on the finest level: b -> x (both [Q][N3]).
+int vcycle_all(rk_ctx* c, const void* b, void* x) {
+    Level& F = c->lv[0];
+    const bool single = c->lv.size() == 1;
+    const bool res_first = single && (c->opt.coarse_cheb_degree % 2 == 1);
+    void* first = res_first ? x : F.y;
+    void* second = res_first ? F.y : x;
+    const int groups = c->opt.mode == RK_BATCHED ? 1 : c->Q;
+    const int ns = c->opt.mode == RK_BATCHED ? c->Q : 1;
+    for (int g = 0; g < groups; ++g) {
+        void* res = nullptr;
+        int rc = vcycle_level(c, 0, g * ns, ns, b, first, second, &res);
+        if (rc) return rc;
+        if (res != x) return fail(c, RK_EHIP, "internal: V-cycle result buffer");
+    }
+    return RK_OK;
+}
+
+// z = P^-1 r (eq. irk:P); r, z fp64 [Q][N3].
+int precondition(rk_ctx* c, const double* r, double* z) {
+    Level& F = c->lv[0];
+    {
+        Timer t(c, C_BASIS);
+        HIPCHK(c, launch_stage_mix(RK_FP64, r, c->pc, F.b, c->mix, c->Q, c->Q, c->N, c->stream));
+    }
+    {
+        Timer t(c, C_BLOCKS);
+        int rc = vcycle_all(c, F.b, F.x);
+        if (rc) return rc;
+    }
+    Timer t(c, C_BASIS);
+    HIPCHK(c, launch_stage_mix(c->pc, F.x, RK_FP64, z, c->mix + 81, c->Q, c->Q, c->N, c->stream));
+    return RK_OK;
+}
+
+// Largest eigenvalue of D^-1 A per level (max over blocks), by power
+// iteration with a Rayleigh-quotient estimate.
+int estimate_eigs(rk_ctx* c) {
+    const int Q = c->Q, dt = c->pc;
+    for (size_t l = 0; l < c->lv.size(); ++l) {
+        Level& L = c->lv[l];
+        if (L.N <= 2) { L.eig_max = 1.0; continue; }
+        HIPCHK(c, launch_random_fill(dt, L.x, L.N, Q, 12345u + 977u * (unsigned)l, c->stream));
+        for (int it = 0; it < c->opt.eig_iterations; ++it) {
+            int rc = op(c, c->k, dt, EPI_STORE, L.blk, L.x, L.y, nullptr, nullptr, L.n, 0, Q, 1, 0, 0);
+            if (rc) return rc;
+            HIPCHK(c, launch_power_partial(c->k, dt, to_stage_scal(L.blk), L.x, L.y, L.b, L.n, Q, c->part, kRedBlocks, c->stream));
+            HIPCHK(c, launch_reduce(c->part, kRedBlocks, 3 * Q, c->scal, 0, c->stream));
+            if (it + 1 < c->opt.eig_iterations)
+                HIPCHK(c, launch_power_normalize(dt, L.b, L.x, c->scal, L.N, Q, c->stream));
+        }
+        double red[3 * RK_MAX_Q];
+        HIPCHK(c, hipMemcpyAsync(red, c->scal, sizeof(double) * 3 * Q, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        double mx = 0.0;
+        for (int s = 0; s < Q; ++s)
+            if (red[3 * s + 1] > 0) mx = std::max(mx, red[3 * s] / red[3 * s + 1]);
+        L.eig_max = mx > 0 ? c->opt.eig_safety * mx : 1.0;
+    }
+    return RK_OK;
+}
+
+// Orthogonalise w against V_0..V_j (classical Gram-Schmidt with one
+// conditional re-orthogonalisation) and normalise into V_{j+1}.
+// Returns h[0..j] and h[j+1] = ||w_orth|| on the host.
+int arnoldi_orth(rk_ctx* c, int j, double* hcol) {
+    const long long qn = (long long)c->Q * c->N3;
+    const int nv = j + 1;
+    double* hs = c->host_scal.data();
+    HIPCHK(c, launch_dots(c->V, nv, qn, c->w, qn, 1, c->part, kRedBlocks, c->stream));
+    HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv + 1, c->scal, 0, c->stream));
+    HIPCHK(c, launch_gs_update(c->V, nv, qn, c->scal, c->w, qn, c->part, kRedBlocks, c->stream));
+    HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream));
+    HIPCHK(c, hipMemcpyAsync(hs, c->scal, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < nv; ++i) hcol[i] = hs[i];
+    const double w2 = hs[nv], w2o = hs[nv + 1];
+    double nrm2 = w2o;
+    if (w2o < 0.5 * w2) {
+        HIPCHK(c, launch_dots(c->V, nv, qn, c->w, qn, 0, c->part, kRedBlocks, c->stream));
+        HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv, c->scal2, 0, c->stream));
+        HIPCHK(c, launch_gs_update(c->V, nv, qn, c->scal2, c->w, qn, c->part, kRedBlocks, c->stream));
+        HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream));
+        HIPCHK(c, hipMemcpyAsync(hs, c->scal2, sizeof(double) * nv, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(hs + nv + 1, c->scal + nv + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int i = 0; i < nv; ++i) hcol[i] += hs[i];
+        nrm2 = hs[nv + 1];
+    }
+    hcol[nv] = std::sqrt(std::max(nrm2, 0.0));
+    if (hcol[nv] > 0)
+        HIPCHK(c, launch_normalize(c->V + (long long)nv * qn, c->w, c->scal + nv + 1, qn, c->stream));
+    return RK_OK;
+}
+
+double device_norm2(rk_ctx* c, const double* x, long long n, int* rc) {
+    hipError_t e = launch_dots(nullptr, 0, 0, x, n, 1, c->part, kRedBlocks, c->stream);
+    if (e == hipSuccess) e = launch_reduce(c->part, kRedBlocks, 1, c->scal, 0, c->stream);
+    double v = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&v, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    *rc = e == hipSuccess ? RK_OK : fail(c, RK_EHIP, std::string("norm: ") + hipGetErrorString(e));
+    return v;
+}
+
+int apply_cala(rk_ctx* c, const double* u, double* v, const double* b) {
+    Timer t(c, C_VMULT);
+    return op(c, c->k, RK_FP64, b ? EPI_RESID : EPI_STORE, c->form[F_CALA], u, v, b, nullptr,
+              c->n, 0, c->Q, c->Q, 0, 0);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void rk_default_options(rk_options* o) {
+    if (!o) return;
+    o->precision = RK_PREC_FP64;
+    o->mode = RK_BATCHED;
+    o->rtol = 1e-10;
+    o->max_iter = 200;
+    o->restart = 30;
+    o->cheb_degree = 3;
+    o->coarse_cheb_degree = 3;
+    o->cheb_range = 15.0;
+    o->eig_safety = 1.2;
+    o->eig_iterations = 30;
+    o->eig_max = nullptr;
+    o->timing = 0;
+}
+
+int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {
+    if (!bytes) return fail(nullptr, RK_EINVAL, "bytes is NULL");
+    rk_ctx c;
+    int rc = setup_sizes(c, mesh, degree, Q, opt);
+    if (rc) return rc;
+    *bytes = carve(c, nullptr);
+    return RK_OK;
+}
+
+int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_options* opt, void* d_workspace,
+              size_t workspace_bytes, void* hip_stream, rk_ctx** out) {
+    if (!out) return fail(nullptr, RK_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!(tau > 0.0)) return fail(nullptr, RK_EINVAL, "tau must be positive");
+    rk_ctx* c = new rk_ctx();
+    int rc = setup_sizes(*c, mesh, degree, Q, opt);
+    if (rc) { delete c; return rc; }
+    c->tau = tau;
+    if (c->opt.eig_max) {
+        c->eig_user.assign(c->opt.eig_max, c->opt.eig_max + c->lv.size());
+        for (double v : c->eig_user)
+            if (!(v > 0.0)) { delete c; return fail(nullptr, RK_EINVAL, "eig_max entries must be positive"); }
+    }
+    c->opt.eig_max = nullptr;
+    const size_t need = carve(*c, nullptr);
+    if (!d_workspace || workspace_bytes < need) {
+        delete c;
+        return fail(nullptr, RK_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    }
+    if (((uintptr_t)d_workspace) % kAlign) { delete c; return fail(nullptr, RK_EINVAL, "workspace not 256-byte aligned"); }
+    carve(*c, (char*)d_workspace);
+    c->stream = (hipStream_t)hip_stream;
+    c->host_scal.assign(c->opt.restart + 16, 0.0);
+    std::string msg;
+    if (!build_tableau(Q, c->tab, msg)) { delete c; return fail(nullptr, RK_EINVAL, msg); }
+    build_element(degree, c->el);
+    for (int f = 0; f < F_NFORMS; ++f) c->form[f] = make_coeffs(*c, c->h, f);
+    for (auto& L : c->lv) L.blk = make_coeffs(*c, L.h, F_BLOCKS);
+    // small Q x Q mixing data: S^-1, S, and the right-hand-side coefficients
+    std::vector<double> mix(4 * 81, 0.0);
+    for (int i = 0; i < Q * Q; ++i) { mix[i] = c->tab.Sinv[i]; mix[81 + i] = c->tab.S[i]; }
+    hipError_t e = hipMemcpyAsync(c->mix, mix.data(), mix.size() * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { delete c; return fail(nullptr, RK_EHIP, hipGetErrorString(e)); }
+    if (!c->eig_user.empty()) {
+        for (size_t l = 0; l < c->lv.size(); ++l) c->lv[l].eig_max = c->eig_user[l];
+    } else if ((rc = estimate_eigs(c))) {
+        g_create_error = c->err; delete c; return rc;
+    }
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { delete c; return fail(nullptr, RK_EHIP, hipGetErrorString(e)); }
+    *out = c;
+    return RK_OK;
+}
+
+int rk_destroy(rk_ctx* c) {
+    if (!c) return RK_EINVAL;
+    for (auto& e : c->event_pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    delete c;
+    return RK_OK;
+}
+
+int rk_info(const rk_ctx* c, rk_info_t* o) {
+    if (!c || !o) return RK_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->N = c->N; o->n_cells = c->n; o->degree = c->k; o->Q = c->Q; o->n_levels = (int)c->lv.size();
+    for (size_t l = 0; l < c->lv.size(); ++l) { o->level_cells[l] = c->lv[l].n; o->eig_max[l] = c->lv[l].eig_max; }
+    o->tau = c->tau; o->h = c->h;
+    const int Q = c->Q;
+    for (int i = 0; i < Q * Q; ++i) {
+        o->A[i] = c->tab.A[i]; o->Ainv[i] = c->tab.Ainv[i]; o->L[i] = c->tab.L[i];
+        o->S[i] = c->tab.S[i]; o->Sinv[i] = c->tab.Sinv[i];
+    }
+    for (int i = 0; i < Q; ++i) { o->b[i] = c->tab.b[i]; o->c[i] = c->tab.c[i]; o->lambda[i] = c->tab.lam[i]; }
+    for (int i = 0; i <= c->k; ++i) o->nodes[i] = c->el.nodes[i];
+    return RK_OK;
+}
+
+int rk_apply_operator(rk_ctx* c, int form, int dtype, const void* u, void* v) {
+    if (!c) return RK_EINVAL;
+    if (!u || !v) return fail(c, RK_EINVAL, "NULL vector");
+    if (form < 0 || form >= F_NFORMS) return fail(c, RK_EINVAL, "bad operator form");
+    if (dtype != RK_FP64 && dtype != RK_FP32) return fail(c, RK_EINVAL, "bad dtype");
+    const int ns = (form == F_K || form == F_M) ? 1 : c->Q;
+    const size_t bytes = dsize(dtype) * (size_t)ns * c->N3;
+    if ((const char*)u < (const char*)v + bytes && (const char*)v < (const char*)u + bytes)
+        return fail(c, RK_EINVAL, "u and v overlap");
+    return op(c, c->k, dtype, EPI_STORE, c->form[form], u, v, nullptr, nullptr, c->n, 0, ns, c->Q, 0, 0);
+}
+
+int rk_vcycle(rk_ctx* c, int dtype, const void* b, void* x) {
+    if (!c) return RK_EINVAL;
+    if (!b || !x) return fail(c, RK_EINVAL, "NULL vector");
+    if (dtype != c->pc) return fail(c, RK_EINVAL, "dtype must match the preconditioner precision");
+    const size_t bytes = dsize(dtype) * (size_t)c->Q * c->N3;
+    if ((const char*)b < (const char*)x + bytes && (const char*)x < (const char*)b + bytes)
+        return fail(c, RK_EINVAL, "b and x overlap");
+    return vcycle_all(c, b, x);
+}
+
+int rk_apply_preconditioner(rk_ctx* c, const double* r, double* z) {
+    if (!c) return RK_EINVAL;
+    if (!r || !z) return fail(c, RK_EINVAL, "NULL vector");
+    return precondition(c, r, z);
+}
+
+int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gamma, rk_stats* stats) {
+    (void)t_n;
+    if (!c) return RK_EINVAL;
+    if (!y) return fail(c, RK_EINVAL, "y is NULL");
+    if (G && !gamma) return fail(c, RK_EINVAL, "gamma is NULL while G is given");
+    const int Q = c->Q, m = c->opt.restart;
+    const long long qn = (long long)Q * c->N3;
+    c->pool_used = 0;
+    rk_stats st{};
+    int rc;
+    // Right-hand side of eq. (irk:A): rhs_i = sum_j Ainv_ij (gamma_j G - K y).
+    {
+        Timer t(c, C_RHS);
+        rc = op(c, c->k, RK_FP64, EPI_STORE, c->form[F_K], y, c->Ky, nullptr, nullptr, c->n, 0, 1, 1, 0, 0);
+        if (rc) return rc;
+        double cf[2 * RK_MAX_Q];
+        for (int i = 0; i < Q; ++i) {
+            double c1 = 0.0, c2 = 0.0;
+            for (int j = 0; j < Q; ++j) {
+                c1 += c->tab.Ainv[i * Q + j] * (G ? gamma[j] : 0.0);
+                c2 -= c->tab.Ainv[i * Q + j];
+            }
+            cf[i] = c1; cf[RK_MAX_Q + i] = c2;
+        }
+        HIPCHK(c, hipMemcpyAsync(c->mix + 162, cf, sizeof(cf), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));   // cf lives on the host stack
+        HIPCHK(c, launch_rhs_mix(G, c->Ky, c->rhs, c->mix + 162, c->mix + 162 + RK_MAX_Q, Q, c->N3, c->stream));
+    }
+    const double bnorm = std::sqrt(device_norm2(c, c->rhs, qn, &rc));
+    if (rc) return rc;
+    HIPCHK(c, launch_fill(RK_FP64, c->kv, qn, 0.0, c->stream));
+    HIPCHK(c, launch_copy(RK_FP64, c->rhs, c->r, qn, c->stream));
+    int its = 0, vcyc = 0;
+    double rnorm = bnorm;
+    bool converged = bnorm == 0.0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), yv(m);
+    while (!converged && its < c->opt.max_iter) {
+        rnorm = std::sqrt(device_norm2(c, c->r, qn, &rc));
+        if (rc) return rc;
+        if (rnorm <= c->opt.rtol * bnorm) { converged = true; break; }
+        {
+            // V_0 = r / ||r||; device_norm2 left ||r||^2 in scal[0]
+            Timer t(c, C_REST);
+            HIPCHK(c, launch_normalize(c->V, c->r, c->scal, qn, c->stream));
+        }
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = rnorm;
+        int jd = 0;
+        for (int j = 0; j < m && its < c->opt.max_iter; ++j) {
+            rc = precondition(c, c->V + (long long)j * qn, c->Z + (long long)j * qn);
+            if (rc) return rc;
+            vcyc += c->opt.mode == RK_BATCHED ? 1 : Q;
+            rc = apply_cala(c, c->Z + (long long)j * qn, c->w, nullptr);
+            if (rc) return rc;
+            {
+                Timer t(c, C_REST);
+                rc = arnoldi_orth(c, j, hcol.data());
+                if (rc) return rc;
+            }
+            for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = hcol[i];
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+            const double d = std::hypot(a, b);
+            cs[j] = d > 0 ? a / d : 1.0;
+            sn[j] = d > 0 ? b / d : 0.0;
+            H[(size_t)j * m + j] = d;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++its;
+            jd = j + 1;
+            if (std::fabs(g[j + 1]) <= c->opt.rtol * bnorm || hcol[j + 1] == 0.0) break;
+        }
+        // y = H^-1 g (upper triangular), k += Z y
+        for (int i = jd - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < jd; ++l) s -= H[(size_t)i * m + l] * yv[l];
+            yv[i] = s / H[(size_t)i * m + i];
+        }
+        {
+            Timer t(c, C_REST);
+            HIPCHK(c, hipMemcpyAsync(c->ycoef, yv.data(), sizeof(double) * jd, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            HIPCHK(c, launch_combine(c->kv, RK_FP64, c->Z, jd, qn, c->ycoef, qn, c->stream));
+        }
+        rc = apply_cala(c, c->kv, c->r, c->rhs);   // true residual r = rhs - A k
+        if (rc) return rc;
+    }
+    if (!converged) {
+        rnorm = std::sqrt(device_norm2(c, c->r, qn, &rc));
+        if (rc) return rc;
+        converged = rnorm <= c->opt.rtol * bnorm;
+    }
+    st.iterations = its;
+    st.vcycles = vcyc;
+    st.rel_residual = bnorm > 0 ? rnorm / bnorm : 0.0;
+    if (converged) {
+        Timer t(c, C_REST);
+        HIPCHK(c, launch_stage_combine(y, c->kv, c->tab.b, c->tau, Q, c->N3, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->opt.timing) {
+        double tt[C_N] = {0};
+        for (size_t i = 0; i < c->pool_used; ++i) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, c->event_pool[i].a, c->event_pool[i].b);
+            tt[c->event_pool[i].comp] += ms * 1e-3;
+        }
+        st.t_rhs = tt[C_RHS]; st.t_vmult = tt[C_VMULT]; st.t_basis = tt[C_BASIS];
+        st.t_blocks = tt[C_BLOCKS]; st.t_rest = tt[C_REST];
+    }
+    if (stats) *stats = st;
+    if (!converged) return fail(c, RK_ENOCONV, "FGMRES did not reach rtol within max_iter");
+    return RK_OK;
+}
+
+const char* rk_last_error(const rk_ctx* c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Internal declarations shared by the host driver and the HIP kernel units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rk.h"
+
+namespace rk {
+
+// ---------------------------------------------------------------------------
+// Host-side mathematics (long double; rounded to double for the device).
+// ---------------------------------------------------------------------------
+
+// Radau IIA tableau and the factors of the preconditioner of eq. (irk:P).
+struct Tableau {
+    int Q = 0;
+    double A[RK_MAX_Q * RK_MAX_Q], b[RK_MAX_Q], c[RK_MAX_Q];
+    double Ainv[RK_MAX_Q * RK_MAX_Q];
+    double L[RK_MAX_Q * RK_MAX_Q], U[RK_MAX_Q * RK_MAX_Q];
+    double S[RK_MAX_Q * RK_MAX_Q], Sinv[RK_MAX_Q * RK_MAX_Q];
+    double lam[RK_MAX_Q];
+};
+// Returns false (with a message) if a factorisation breaks down.
+bool build_tableau(int Q, Tableau& t, std::string& err);
+
+// 1D reference element of degree k on [0,1] (Gauss-Lobatto nodes).
+struct Element1D {
+    int k = 0;
+    double nodes[RK_MAX_DEGREE + 1];
+    double mass[(RK_MAX_DEGREE + 1) * (RK_MAX_DEGREE + 1)];    // int l_a l_b
+    double stiff[(RK_MAX_DEGREE + 1) * (RK_MAX_DEGREE + 1)];   // int l_a' l_b'
+    // prolongation from one coarse cell to its two halves: (2k+1) x (k+1)
+    double prol[(2 * RK_MAX_DEGREE + 1) * (RK_MAX_DEGREE + 1)];
+};
+void build_element(int k, Element1D& e);
+
+// Per-stage scales of the diagonal-mix operator v_s = alpha_s Mref u_s +
+// beta_s Kref u_s, where Mref / Kref are the Kronecker products of the unit-cell
+// 1D element matrices and the cell size is folded into the scales (h^3 for the
+// mass term, h for the stiffness term).
+struct StageScal {
+    double alpha[RK_MAX_Q] = {};
+    double beta[RK_MAX_Q] = {};
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (implemented in the .hip units).  All return hipError_t.
+// ---------------------------------------------------------------------------
+enum Mix { MIX_DIAG = 0, MIX_DENSE = 1 };
+enum Epi { EPI_STORE = 0, EPI_RESID = 1, EPI_CHEB = 2 };
+
+struct OpLaunch {
+    int k = 0;
+    int dtype = RK_FP64;
+    int mix = MIX_DIAG;
+    int epi = EPI_STORE;
+    const void* u = nullptr;   // input vector base (stage 0)
+    void* v = nullptr;         // output vector base (stage 0)
+    const void* b = nullptr;   // EPI_RESID / EPI_CHEB right-hand side base
+    const void* xo = nullptr;  // EPI_CHEB previous iterate base (nullptr = zero)
+    double alpha[RK_MAX_Q] = {};   // diagonal mix: per-stage scales
+    double beta[RK_MAX_Q] = {};
+    double DM[RK_MAX_Q * RK_MAX_Q] = {};   // dense mix: v_s = M sum_j DM[s][j] u_j
+    double DK[RK_MAX_Q * RK_MAX_Q] = {};   //                + K sum_j DK[s][j] u_j
+    long long stride = 0;      // elements between stages (N^3)
+    int n = 0;                 // cells per direction
+    int s0 = 0, nstage = 1;    // output stages [s0, s0 + nstage)
+    int qin = 1;               // dense: number of input stages
+    double ca = 0.0, cb = 0.0; // EPI_CHEB: x_new = x + ca (x - xo) + cb D^-1 (b - A x)
+    hipStream_t stream = nullptr;
+};
+hipError_t launch_op(const OpLaunch& L);
+
+// One 1D pass of the tensor-product transfer along `axis` (0 = x, 1 = y, 2 = z).
+//   restrict: coarse-length output along axis, fine input;  prolong: the reverse.
+struct TransferLaunch {
+    int k = 0, dtype = RK_FP64;
+    bool restrict_ = true;
+    bool add = false;          // prolong only: out += P in
+    int axis = 0;
+    const void* in = nullptr;
+    void* out = nullptr;
+    int din[3] = {0, 0, 0};    // input dims (x, y, z)
+    int dout[3] = {0, 0, 0};   // output dims
+    long long sin = 0, sout = 0;   // stage strides
+    int nstage = 1;
+    hipStream_t stream = nullptr;
+};
+hipError_t launch_transfer(const TransferLaunch& L);
+
+// x = cb D^-1 b (first Chebyshev step from a zero start), D = diag of the
+// diagonal-mix operator with scales sc, per stage; boundary entries 0.
+hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* b, void* x,
+                             int n, int s0, int nstage, double cb, hipStream_t st);
+
+// out_i = sum_j D[i][j] in_j (D: device doubles, row-major Qout x Qin),
+// computed in double; in/out dtypes independent.  Boundary entries 0.
+hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* out,
+                            const double* D, int qout, int qin, int N, hipStream_t st);
+
+// out_i = c1[i] G + c2[i] w  (fp64), G may be null.  c1, c2: device doubles.
+hipError_t launch_rhs_mix(const double* G, const double* w, double* out, const double* c1,
+                          const double* c2, int Q, long long n3, hipStream_t st);
+
+// Partial dot products: part[blk * nout + l] = sum_{i in blk} X_l[i] * w[i] for
+// l < nvec, and (if self) part[blk * nout + nvec] = sum w[i]^2, nout = nvec + self.
+hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w, long long n,
+                       int self, double* part, int nblocks, hipStream_t st);
+// w -= sum_l h[l] X_l; if norm_part: norm_part[blk] = sum (w_new)^2.
+hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, double* w,
+                            long long n, double* norm_part, int nblocks, hipStream_t st);
+// out[l] (+)= sum_b part[b * nout + l] for l < nout (fixed order).
+hipError_t launch_reduce(const double* part, int nblocks, int nout, double* out, int accumulate,
+                         hipStream_t st);
+// v = w * (1 / sqrt(*nrm2))
+hipError_t launch_normalize(double* v, const double* w, const double* nrm2, long long n,
+                            hipStream_t st);
+// k += sum_j y[j] Z_j   (Z fp64 or fp32)
+hipError_t launch_combine(double* kv, int dtype_z, const void* Z, int nz, long long ld,
+                          const double* y, long long n, hipStream_t st);
+// y += tau sum_i b[i] k_i  (b: host values, passed by value)
+hipError_t launch_stage_combine(double* y, const double* kv, const double* b, double tau, int Q,
+                                long long n3, hipStream_t st);
+hipError_t launch_fill(int dtype, void* x, long long n, double value, hipStream_t st);
+hipError_t launch_copy(int dtype, const void* src, void* dst, long long n, hipStream_t st);
+
+// Power iteration support (per stage, diagonal-mix operator with scales sc):
+// given v and w = A v: z = D^-1 w; part[blk*3*ns + 3 s + {0,1,2}] =
+// {v.w, v.Dv, z.z} restricted to stage s.  Requires nstage <= RK_MAX_Q.
+hipError_t launch_power_partial(int k, int dtype, const StageScal& sc, const void* v,
+                                const void* w, void* z, int n, int nstage, double* part,
+                                int nblocks, hipStream_t st);
+// v_s = z_s / sqrt(zz_s) with zz_s = red[3 s + 2]
+hipError_t launch_power_normalize(int dtype, const void* z, void* v, const double* red, int n,
+                                  int nstage, hipStream_t st);
+// deterministic pseudo-random start vector in [-1,1], zero boundary
+hipError_t launch_random_fill(int dtype, void* x, int N, int nstage, unsigned seed,
+                              hipStream_t st);
+
+}  // namespace rk

@@ -1,0 +1,83 @@
+"""The C-ABI library loads, exports every entry point declared in
+include/rk.h, and its host-only calls (options, workspace sizing, argument
+validation) behave as documented.  No GPU is touched here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "rk.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rk_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_api():
+    names = _declared()
+    for n in ["rk_create", "rk_step", "rk_apply_operator", "rk_vcycle", "rk_workspace_bytes",
+              "rk_destroy", "rk_info", "rk_last_error", "rk_default_options", "rk_apply_preconditioner"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2209_06700_amd import _lib
+    lib = C.CDLL(_lib.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == _declared()
+
+
+def test_default_options():
+    from paper_2209_06700_amd import rk as R
+    o = R.rk_default_options()
+    assert (o.precision, o.mode, o.rtol, o.restart, o.cheb_degree, o.cheb_range) == (0, 0, 1e-10, 30, 3, 15.0)
+    o = R.rk_default_options(precision=R.RK_PREC_MIXED, restart=12)
+    assert o.precision == 1 and o.restart == 12
+    with pytest.raises(TypeError):
+        R.rk_default_options(bogus=1)
+
+
+def test_workspace_bytes_scale_with_problem():
+    from paper_2209_06700_amd import rk as R
+    a = R.rk_workspace_bytes(8, 2, 2)
+    b = R.rk_workspace_bytes(16, 2, 2)
+    c = R.rk_workspace_bytes(8, 2, 4)
+    assert 0 < a < b and a < c
+    mixed = R.rk_workspace_bytes(32, 4, 3, R.rk_default_options(precision=R.RK_PREC_MIXED))
+    fp64 = R.rk_workspace_bytes(32, 4, 3)
+    assert mixed < fp64
+    # at least the Krylov bases: (2 restart + 1) fp64 vectors of Q N^3
+    N = 32 * 4 + 1
+    assert fp64 > (2 * 30 + 1) * 3 * N ** 3 * 8
+
+
+@pytest.mark.parametrize("args", [(0, 2, 2), (4, 0, 2), (4, 7, 2), (4, 2, 0), (4, 2, 10)])
+def test_invalid_sizes_rejected(args):
+    from paper_2209_06700_amd import rk as R
+    with pytest.raises(R.RKError) as e:
+        R.rk_workspace_bytes(*args)
+    assert e.value.code == R._lib.RK_EINVAL
+
+
+def test_invalid_options_rejected():
+    from paper_2209_06700_amd import rk as R
+    for kw in [dict(precision=5), dict(mode=3), dict(rtol=0.0), dict(restart=0), dict(cheb_degree=0),
+               dict(cheb_range=1.0)]:
+        with pytest.raises(R.RKError):
+            R.rk_workspace_bytes(4, 2, 2, R.rk_default_options(**kw))
+
+
+def test_create_rejects_missing_workspace_without_touching_the_gpu():
+    from paper_2209_06700_amd import _lib
+    lib = _lib.LIB
+    mesh = _lib.rk_mesh(4)
+    out = C.c_void_p()
+    rc = lib.rk_create(C.byref(mesh), 2, 2, 0.1, None, None, 0, None, C.byref(out))
+    assert rc == _lib.RK_EWORKSPACE and not out.value
+    assert b"workspace" in lib.rk_last_error(None)
+    rc = lib.rk_create(C.byref(mesh), 2, 2, -1.0, None, None, 0, None, C.byref(out))
+    assert rc == _lib.RK_EINVAL

@@ -1,0 +1,162 @@
+"""GPU parity of rk_apply_operator against the oracle.
+
+Small meshes: every output node is compared with the assembled (cell-loop)
+sparse matrices of the oracle.  Sizes are chosen so that the grids span
+several tiles and z-chunks of the kernel and end in ragged tiles, including
+grids whose last node falls exactly on a tile edge.  Full size: sampled nodes
+against the oracle's single-row evaluation.
+
+Tolerance, element-wise: |v - v_ref| <= c * eps * (|Op| |u|) with eps the unit
+roundoff of the dtype and c = 64 (fp64) / 128 (fp32): the kernel evaluates
+each output as a sum of at most 3 (2k+1)^3-term products in a different order
+than the assembled matrix, so every term can carry a few roundings.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2209_06700_amd import rk
+    return rk
+
+
+def _oracle_forms(p, tab, tau, u):
+    """Reference outputs and |Op||u| scales on the full grid for all forms."""
+    Q = tab.Q
+    ui = p.to_int(u.reshape(Q, -1))
+    Mu = np.stack([p.M @ x for x in ui])
+    Ku = np.stack([p.K @ x for x in ui])
+    aM, aK = abs(p.M), abs(p.K)
+    Mab = np.stack([aM @ abs(x) for x in ui])
+    Kab = np.stack([aK @ abs(x) for x in ui])
+    out = {
+        "CALA": (tab.Ainv @ Mu + tau * Ku, abs(tab.Ainv) @ Mab + tau * Kab),
+        "STAGE": (Mu + tau * (tab.A @ Ku), Mab + tau * (abs(tab.A) @ Kab)),
+        "BLOCKS": (tab.lam[:, None] * Mu + tau * Ku, tab.lam[:, None] * Mab + tau * Kab),
+        "K": (Ku[:1], Kab[:1]),
+        "M": (Mu[:1], Mab[:1]),
+    }
+    return {k: (p.to_full(v), p.to_full(s)) for k, (v, s) in out.items()}
+
+
+CASES = [  # (n, k, Q): multi-tile, ragged and tile-edge grids for every degree
+    (1, 1, 1), (33, 1, 2), (16, 1, 3),
+    (2, 2, 2), (17, 2, 3), (8, 2, 2),
+    (3, 3, 3), (11, 3, 2),
+    (2, 4, 4), (8, 4, 3), (9, 4, 2),
+    (7, 5, 2), (3, 5, 5),
+    (6, 6, 2), (2, 6, 1),
+]
+
+
+@pytest.mark.parametrize("n,k,Q", CASES)
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_operator_parity_small(R, n, k, Q, dtype):
+    from oracle.assemble import Problem
+    from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import random_vector
+    tau = 0.013
+    print(f"operator parity n={n} k={k} Q={Q} {dtype}", flush=True)
+    p = Problem(n, k)
+    tab = RadauIIA(Q)
+    N = n * k + 1
+    td = torch.float64 if dtype == "fp64" else torch.float32
+    u_np = random_vector((Q, N ** 3), seed=100 * n + 10 * k + Q, zero_boundary_N=N)
+    u_np = u_np.astype(np.float32).astype(np.float64) if dtype == "fp32" else u_np
+    ref = _oracle_forms(p, tab, tau, u_np)
+    ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(), eig_max=[1.0] * len(__import__(
+        "oracle.multigrid", fromlist=["level_sizes"]).level_sizes(n)))
+    eps = np.finfo(np.float64 if dtype == "fp64" else np.float32).eps
+    c = 64 if dtype == "fp64" else 128
+    try:
+        u = torch.tensor(u_np, dtype=td, device="cuda")
+        # garbage in the boundary entries of the input must be ignored
+        u3 = u.view(Q, N, N, N)
+        u3[:, 0] = 7.0
+        u3[:, :, :, -1] = -3.0
+        for name, form in [("CALA", R.RK_OP_CALA), ("STAGE", R.RK_OP_STAGE), ("BLOCKS", R.RK_OP_BLOCKS),
+                           ("K", R.RK_OP_K), ("M", R.RK_OP_M)]:
+            ns = 1 if name in ("K", "M") else Q
+            v = torch.full((ns * N ** 3,), float("nan"), dtype=td, device="cuda")
+            R.rk_apply_operator(ctx, form, u[: ns * N ** 3].contiguous() if ns == 1 else u, v)
+            torch.cuda.synchronize()
+            got = v.double().cpu().numpy().reshape(ns, -1)
+            want, scale = ref[name]
+            assert np.all(np.isfinite(got)), name
+            err = np.abs(got - want)
+            tol = c * eps * scale + 1e-300
+            bad = err > tol
+            assert not bad.any(), (name, float(err.max()), float((err / (scale + 1e-300)).max()))
+    finally:
+        R.rk_destroy(ctx)
+
+
+@pytest.mark.parametrize("n,k,Q,dtype,form", [
+    (64, 4, 4, "fp32", "BLOCKS"),     # mixed-precision block operator of the 64^3 Q_4 workload
+    (64, 4, 4, "fp64", "CALA"),       # outer operator of the same workload
+    (32, 4, 3, "fp64", "CALA"),       # 32^3 Q_4 workloads, Q = 3 and 5
+    (32, 4, 5, "fp64", "CALA"),
+    (32, 4, 5, "fp64", "BLOCKS"),
+])
+def test_operator_parity_full_size_sampled(R, n, k, Q, dtype, form):
+    """Full-size grids in the launch configuration of the benchmark: sampled
+    nodes (random, plus tile/chunk edges and near-boundary nodes) against the
+    oracle's one-row-at-a-time evaluation."""
+    from oracle.pointwise import PointwiseOperator
+    from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords, random_vector
+    print(f"full-size sampled parity n={n} k={k} Q={Q} {dtype} {form}", flush=True)
+    tau = 5e-4
+    N = n * k + 1
+    tab = RadauIIA(Q)
+    td = torch.float64 if dtype == "fp64" else torch.float32
+    from oracle.multigrid import level_sizes
+    ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(restart=1), eig_max=[1.0] * len(level_sizes(n)))
+    try:
+        x1 = grid_coords(R.rk_info(ctx)["nodes"], n)
+        # smooth data in stage 0, rough data elsewhere
+        u_np = np.stack([fourier_field(x1, seed=0)] + [random_vector(N ** 3, seed=s, zero_boundary_N=N)
+                                                        for s in range(1, Q)])
+        if dtype == "fp32":
+            u_np = u_np.astype(np.float32).astype(np.float64)
+        u = torch.tensor(u_np, dtype=td, device="cuda")
+        v = torch.empty_like(u)
+        fid = {"BLOCKS": R.RK_OP_BLOCKS, "CALA": R.RK_OP_CALA}[form]
+        R.rk_apply_operator(ctx, fid, u, v)
+        torch.cuda.synchronize()
+        got = v.double().cpu().numpy()
+    finally:
+        R.rk_destroy(ctx)
+    rng = np.random.default_rng(5)
+    nodes = [tuple(int(t) for t in rng.integers(0, N, 3)) for _ in range(60)]
+    edges = [0, 1, 2, k, k + 1, 31, 32, 33, N // 2, N - 3, N - 2, N - 1]
+    nodes += [(a, b, c) for a, b, c in zip(edges, edges[::-1], edges[3:] + edges[:3])]
+    nodes += [(32, 32, 32), (33, 31, 30), (N - 2, 1, N - 2), (1, N - 2, 32)]
+    pw = PointwiseOperator(n, k)
+    Mu, Ku, Mab, Kab = [], [], [], []
+    for s in range(Q):
+        m, kk = pw.rows(u_np[s], nodes)
+        ma, ka = pw.rows(np.abs(u_np[s]), nodes)
+        Mu.append(m); Ku.append(kk); Mab.append(np.abs(ma)); Kab.append(np.abs(ka))
+    Mu, Ku, Mab, Kab = map(np.array, (Mu, Ku, Mab, Kab))
+    if form == "BLOCKS":
+        want = tab.lam[:, None] * Mu + tau * Ku
+        scale = tab.lam[:, None] * Mab + tau * Kab
+    else:
+        want = tab.Ainv @ Mu + tau * Ku
+        scale = abs(tab.Ainv) @ Mab + tau * Kab
+    idx = [a + N * (b + N * c) for (a, b, c) in nodes]
+    eps = np.finfo(np.float64 if dtype == "fp64" else np.float32).eps
+    c = 64 if dtype == "fp64" else 128
+    err = np.abs(got[:, idx] - want)
+    assert np.all(err <= c * eps * scale + 1e-300), float((err / (scale + 1e-300)).max())
+    # boundary faces are exactly zero
+    g = got.reshape(Q, N, N, N)
+    for face in (g[:, 0], g[:, -1], g[:, :, 0], g[:, :, -1], g[:, :, :, 0], g[:, :, :, -1]):
+        assert not face.any()

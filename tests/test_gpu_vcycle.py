@@ -1,0 +1,141 @@
+"""GPU parity of the batched block V-cycle and of the preconditioner P^-1
+(eq. irk:P) against the oracle's assembled multigrid, with the Chebyshev
+bounds passed explicitly so that both sides run the same iteration.
+
+fp64: |x - x_ref| <= 1e-12 max|x_ref| (the V-cycle is a fixed linear map of
+modest norm; both sides round differently in every product).  Mixed
+precision: the fp32 V-cycle against the fp64 oracle within 1e-4 relative
+(fp32 unit roundoff 6e-8 amplified by the V-cycle's operator norm and depth).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2209_06700_amd import rk
+    return rk
+
+
+def _oracle_mg(n, k, Q, tau, degree, coarse_degree):
+    from oracle.multigrid import BlockMG, Hierarchy
+    from oracle.tableau import RadauIIA
+    tab = RadauIIA(Q)
+    hier = Hierarchy(n, k)
+    mg = BlockMG(hier, tab.lam, tau, degree=degree, coarse_degree=coarse_degree, cheb_range=15.0)
+    return tab, hier, mg
+
+
+VCASES = [(8, 2, 2, 0.05, 3, 3), (4, 3, 3, 0.01, 2, 4), (16, 1, 2, 0.1, 3, 3), (6, 2, 1, 0.2, 3, 3),
+          (2, 4, 4, 0.003, 3, 2), (5, 2, 2, 0.05, 3, 3)]
+
+
+@pytest.mark.parametrize("n,k,Q,tau,deg,cdeg", VCASES)
+@pytest.mark.parametrize("mode", ["batched", "per_stage"])
+def test_vcycle_parity_fp64(R, n, k, Q, tau, deg, cdeg, mode):
+    from paper_2209_06700_amd.synthetic import random_vector
+    print(f"vcycle fp64 n={n} k={k} Q={Q} {mode}", flush=True)
+    tab, hier, mg = _oracle_mg(n, k, Q, tau, deg, cdeg)
+    fine = hier.levels[0]
+    N = n * k + 1
+    opts = R.rk_default_options(cheb_degree=deg, coarse_cheb_degree=cdeg, cheb_range=15.0,
+                                mode=R.RK_BATCHED if mode == "batched" else R.RK_PER_STAGE)
+    ctx = R.rk_create(n, k, Q, tau, opts, eig_max=list(mg.eig_max))
+    try:
+        b_np = random_vector((Q, N ** 3), seed=7 + n, zero_boundary_N=N)
+        b = torch.tensor(b_np, device="cuda")
+        x = torch.full_like(b, float("nan"))
+        R.rk_vcycle(ctx, b, x)
+        torch.cuda.synchronize()
+        got = x.cpu().numpy()
+        want = fine.to_full(mg.vcycle(fine.to_int(b_np)))
+        scale = np.abs(want).max()
+        assert np.abs(got - want).max() <= 1e-12 * scale, np.abs(got - want).max() / scale
+    finally:
+        R.rk_destroy(ctx)
+
+
+def test_batched_and_per_stage_are_identical(R):
+    """Same arithmetic in a different launch grouping: bitwise equal."""
+    from paper_2209_06700_amd.synthetic import random_vector
+    n, k, Q, tau = 8, 3, 3, 0.02
+    N = n * k + 1
+    b = torch.tensor(random_vector((Q, N ** 3), seed=3, zero_boundary_N=N), device="cuda")
+    outs = []
+    for mode in (R.RK_BATCHED, R.RK_PER_STAGE):
+        for prec, dt in ((R.RK_PREC_FP64, torch.float64), (R.RK_PREC_MIXED, torch.float32)):
+            ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(mode=mode, precision=prec),
+                              eig_max=[2.0, 2.1, 2.2, 2.3])
+            bb = b.to(dt)
+            x = torch.empty_like(bb)
+            R.rk_vcycle(ctx, bb, x)
+            torch.cuda.synchronize()
+            outs.append((mode, prec, x.cpu()))
+            R.rk_destroy(ctx)
+    assert torch.equal(outs[0][2], outs[2][2])
+    assert torch.equal(outs[1][2], outs[3][2])
+
+
+@pytest.mark.parametrize("n,k,Q,tau", [(8, 2, 2, 0.05), (4, 4, 3, 0.01)])
+def test_vcycle_mixed_precision(R, n, k, Q, tau):
+    from paper_2209_06700_amd.synthetic import random_vector
+    tab, hier, mg = _oracle_mg(n, k, Q, tau, 3, 3)
+    fine = hier.levels[0]
+    N = n * k + 1
+    ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(precision=R.RK_PREC_MIXED), eig_max=list(mg.eig_max))
+    try:
+        b_np = random_vector((Q, N ** 3), seed=11, zero_boundary_N=N).astype(np.float32)
+        b = torch.tensor(b_np, device="cuda")
+        x = torch.empty_like(b)
+        R.rk_vcycle(ctx, b, x)
+        torch.cuda.synchronize()
+        got = x.double().cpu().numpy()
+        want = fine.to_full(mg.vcycle(fine.to_int(b_np.astype(np.float64))))
+        assert np.abs(got - want).max() <= 1e-4 * np.abs(want).max()
+    finally:
+        R.rk_destroy(ctx)
+
+
+@pytest.mark.parametrize("n,k,Q,tau", [(8, 2, 2, 0.05), (4, 3, 4, 0.02)])
+def test_preconditioner_parity(R, n, k, Q, tau):
+    """P^-1 r = (S (x) I) V-cycles (S^-1 (x) I) r, fp64."""
+    from oracle.multigrid import BlockPreconditioner
+    from paper_2209_06700_amd.synthetic import random_vector
+    tab, hier, mg = _oracle_mg(n, k, Q, tau, 3, 3)
+    fine = hier.levels[0]
+    N = n * k + 1
+    ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(), eig_max=list(mg.eig_max))
+    try:
+        r_np = random_vector((Q, N ** 3), seed=13, zero_boundary_N=N)
+        r = torch.tensor(r_np, device="cuda")
+        z = torch.empty_like(r)
+        R.rk_apply_preconditioner(ctx, r, z)
+        torch.cuda.synchronize()
+        want = fine.to_full(BlockPreconditioner(tab, mg).apply(fine.to_int(r_np)))
+        got = z.cpu().numpy()
+        assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
+    finally:
+        R.rk_destroy(ctx)
+
+
+@pytest.mark.parametrize("n,k,Q,tau", [(8, 2, 2, 0.05), (16, 2, 3, 0.01), (4, 4, 4, 0.001)])
+def test_eigen_estimate_is_safe(R, n, k, Q, tau):
+    """The power-iteration bound of every level lies in [1, 1.2] times the exact
+    largest eigenvalue of D^-1 A over the blocks (it is 1.2 x a Rayleigh
+    quotient, which never exceeds the maximum)."""
+    tab, hier, mg = _oracle_mg(n, k, Q, tau, 3, 3)
+    ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(eig_iterations=40))
+    try:
+        est = R.rk_info(ctx)["eig_max"]
+    finally:
+        R.rk_destroy(ctx)
+    for l in range(hier.nlevels):
+        if hier.levels[l].M.shape[0] == 0:
+            continue
+        exact = mg.max_eig_exact(l)
+        assert 0.9 * 1.2 * exact <= est[l] <= 1.2 * exact * (1 + 1e-9), (l, est[l], exact)
