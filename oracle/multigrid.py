@@ -119,6 +119,8 @@ class BlockMG:
         best = 0.0
         for Ai, Di in zip(self.A[l], self.Dinv[l]):
             n = Ai.shape[0]
+            if n == 0:          # no interior unknowns on this level
+                return 1.0
             if n <= 400:
                 ev = np.linalg.eigvalsh((Ai.toarray() * np.sqrt(Di)[:, None]) * np.sqrt(Di)[None, :])
                 best = max(best, ev[-1])

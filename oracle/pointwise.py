@@ -33,12 +33,16 @@ class PointwiseOperator:
             out.append((e - 1, k))
         return out
 
-    def rows(self, u, nodes):
+    def rows(self, u, nodes, absolute=False):
         """(M u) and (K u) at the given nodes.
 
         u: full-grid vector (N^3,) with zero boundary entries (boundary values
         are ignored: homogeneous Dirichlet).  nodes: iterable of (ix, iy, iz).
-        Boundary nodes return 0 (the Dirichlet-eliminated operator)."""
+        Boundary nodes return 0 (the Dirichlet-eliminated operator).  With
+        absolute=True the entries of the element matrices are replaced by their
+        absolute values (the |M| |u| bound used for rounding tolerances)."""
+        Me = np.abs(self.Me) if absolute else self.Me
+        Ke = np.abs(self.Ke) if absolute else self.Ke
         N, k = self.N, self.k
         u3 = np.asarray(u).reshape(N, N, N).copy()
         u3[0, :, :] = 0; u3[-1, :, :] = 0
@@ -55,7 +59,7 @@ class PointwiseOperator:
                     self._cells_1d(ix), self._cells_1d(iy), self._cells_1d(iz)):
                 loc = u3[ez * k:ez * k + n1, ey * k:ey * k + n1, ex * k:ex * k + n1].reshape(-1)
                 row = ax + n1 * (ay + n1 * az)
-                sm += self.Me[row] @ loc
-                sk += self.Ke[row] @ loc
+                sm += Me[row] @ loc
+                sk += Ke[row] @ loc
             outM.append(sm); outK.append(sk)
         return np.array(outM), np.array(outK)

@@ -333,15 +333,25 @@ struct BVec {
     double v[RK_MAX_Q];
 };
 
+// y <- y + tau sum_i b_i k_i on interior nodes; boundary nodes are set to 0.
 __global__ void __launch_bounds__(kBlock) stage_combine_kernel(double* __restrict__ y, const double* __restrict__ kv,
-                                                               BVec b, double tau, int Q, long long n3) {
+                                                               BVec b, double tau, int Q, int N) {
+    const long long n3 = (long long)N * N * N;
+    const int nK = N - 1;
     for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n3;
          r += (long long)gridDim.x * blockDim.x) {
-        double acc = 0.0;
+        const int z = (int)(r / ((long long)N * N));
+        const int rr = (int)(r - (long long)z * N * N);
+        const int yy = rr / N, x = rr - yy * N;
+        double out = 0.0;
+        if (x > 0 && x < nK && yy > 0 && yy < nK && z > 0 && z < nK) {
+            double acc = 0.0;
 #pragma unroll
-        for (int i = 0; i < RK_MAX_Q; ++i)
-            if (i < Q) acc = fma(b.v[i], kv[(long long)i * n3 + r], acc);
-        y[r] = fma(tau, acc, y[r]);
+            for (int i = 0; i < RK_MAX_Q; ++i)
+                if (i < Q) acc = fma(b.v[i], kv[(long long)i * n3 + r], acc);
+            out = fma(tau, acc, y[r]);
+        }
+        y[r] = out;
     }
 }
 
@@ -516,10 +526,11 @@ hipError_t launch_combine(double* kv, int dtype_z, const void* Z, int nz, long l
 }
 
 hipError_t launch_stage_combine(double* y, const double* kv, const double* b, double tau, int Q,
-                                long long n3, hipStream_t st) {
+                                int N, hipStream_t st) {
     BVec bv;
     for (int i = 0; i < RK_MAX_Q; ++i) bv.v[i] = i < Q ? b[i] : 0.0;
-    stage_combine_kernel<<<grid_for(n3), kBlock, 0, st>>>(y, kv, bv, tau, Q, n3);
+    const long long n3 = (long long)N * N * N;
+    stage_combine_kernel<<<grid_for(n3), kBlock, 0, st>>>(y, kv, bv, tau, Q, N);
     return hipGetLastError();
 }
 

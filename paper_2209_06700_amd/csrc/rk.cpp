@@ -759,7 +759,7 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
     st.rel_residual = bnorm > 0 ? rnorm / bnorm : 0.0;
     if (converged) {
         Timer t(c, C_REST);
-        HIPCHK(c, launch_stage_combine(y, c->kv, c->tab.b, c->tau, Q, c->N3, c->stream));
+        HIPCHK(c, launch_stage_combine(y, c->kv, c->tab.b, c->tau, Q, c->N, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (c->opt.timing) {

@@ -123,9 +123,10 @@ hipError_t launch_normalize(double* v, const double* w, const double* nrm2, long
 // k += sum_j y[j] Z_j   (Z fp64 or fp32)
 hipError_t launch_combine(double* kv, int dtype_z, const void* Z, int nz, long long ld,
                           const double* y, long long n, hipStream_t st);
-// y += tau sum_i b[i] k_i  (b: host values, passed by value)
+// y += tau sum_i b[i] k_i on interior nodes, y = 0 on boundary nodes
+// (b: host values, passed by value; N nodes per direction)
 hipError_t launch_stage_combine(double* y, const double* kv, const double* b, double tau, int Q,
-                                long long n3, hipStream_t st);
+                                int N, hipStream_t st);
 hipError_t launch_fill(int dtype, void* x, long long n, double value, hipStream_t st);
 hipError_t launch_copy(int dtype, const void* src, void* dst, long long n, hipStream_t st);
 

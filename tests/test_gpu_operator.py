@@ -84,7 +84,7 @@ def test_operator_parity_small(R, n, k, Q, dtype):
                            ("K", R.RK_OP_K), ("M", R.RK_OP_M)]:
             ns = 1 if name in ("K", "M") else Q
             v = torch.full((ns * N ** 3,), float("nan"), dtype=td, device="cuda")
-            R.rk_apply_operator(ctx, form, u[: ns * N ** 3].contiguous() if ns == 1 else u, v)
+            R.rk_apply_operator(ctx, form, u.view(-1)[: ns * N ** 3], v)
             torch.cuda.synchronize()
             got = v.double().cpu().numpy().reshape(ns, -1)
             want, scale = ref[name]
@@ -142,8 +142,8 @@ def test_operator_parity_full_size_sampled(R, n, k, Q, dtype, form):
     Mu, Ku, Mab, Kab = [], [], [], []
     for s in range(Q):
         m, kk = pw.rows(u_np[s], nodes)
-        ma, ka = pw.rows(np.abs(u_np[s]), nodes)
-        Mu.append(m); Ku.append(kk); Mab.append(np.abs(ma)); Kab.append(np.abs(ka))
+        ma, ka = pw.rows(np.abs(u_np[s]), nodes, absolute=True)
+        Mu.append(m); Ku.append(kk); Mab.append(ma); Kab.append(ka)
     Mu, Ku, Mab, Kab = map(np.array, (Mu, Ku, Mab, Kab))
     if form == "BLOCKS":
         want = tab.lam[:, None] * Mu + tau * Ku
