@@ -215,15 +215,22 @@ __global__ void __launch_bounds__(kBlock) stage_mix_kernel(const Tin* __restrict
     }
 }
 
+// out_i = c1_i G + c2_i w on interior nodes, 0 on boundary nodes (the load
+// vector's boundary entries belong to eliminated Dirichlet unknowns).
 __global__ void __launch_bounds__(kBlock) rhs_mix_kernel(const double* __restrict__ G, const double* __restrict__ w,
                                                          double* __restrict__ out,
                                                          const double* __restrict__ c1,
-                                                         const double* __restrict__ c2, int Q,
-                                                         long long n3) {
+                                                         const double* __restrict__ c2, int Q, int N) {
+    const long long n3 = (long long)N * N * N;
+    const int nK = N - 1;
     for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n3;
          r += (long long)gridDim.x * blockDim.x) {
-        const double g = G ? G[r] : 0.0;
-        const double wv = w[r];
+        const int z = (int)(r / ((long long)N * N));
+        const int rr = (int)(r - (long long)z * N * N);
+        const int y = rr / N, x = rr - y * N;
+        const bool inner = x > 0 && x < nK && y > 0 && y < nK && z > 0 && z < nK;
+        const double g = (G && inner) ? G[r] : 0.0;
+        const double wv = inner ? w[r] : 0.0;
         for (int i = 0; i < Q; ++i) out[(long long)i * n3 + r] = fma(c1[i], g, c2[i] * wv);
     }
 }
@@ -488,8 +495,9 @@ hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* o
 }
 
 hipError_t launch_rhs_mix(const double* G, const double* w, double* out, const double* c1,
-                          const double* c2, int Q, long long n3, hipStream_t st) {
-    rhs_mix_kernel<<<grid_for(n3), kBlock, 0, st>>>(G, w, out, c1, c2, Q, n3);
+                          const double* c2, int Q, int N, hipStream_t st) {
+    const long long n3 = (long long)N * N * N;
+    rhs_mix_kernel<<<grid_for(n3), kBlock, 0, st>>>(G, w, out, c1, c2, Q, N);
     return hipGetLastError();
 }
 

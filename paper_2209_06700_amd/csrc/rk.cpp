@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -682,7 +683,7 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
         }
         HIPCHK(c, hipMemcpyAsync(c->mix + 162, cf, sizeof(cf), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));   // cf lives on the host stack
-        HIPCHK(c, launch_rhs_mix(G, c->Ky, c->rhs, c->mix + 162, c->mix + 162 + RK_MAX_Q, Q, c->N3, c->stream));
+        HIPCHK(c, launch_rhs_mix(G, c->Ky, c->rhs, c->mix + 162, c->mix + 162 + RK_MAX_Q, Q, c->N, c->stream));
     }
     const double bnorm = std::sqrt(device_norm2(c, c->rhs, qn, &rc));
     if (rc) return rc;
@@ -732,6 +733,11 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
             g[j] = cs[j] * g[j];
             ++its;
             jd = j + 1;
+            if (std::getenv("RK_DEBUG_ARNOLDI")) {
+                std::fprintf(stderr, "[rk] j=%d |g|/bn=%.3e h:", j, std::fabs(g[j + 1]) / bnorm);
+                for (int i = 0; i <= j + 1; ++i) std::fprintf(stderr, " %.6e", hcol[i]);
+                std::fprintf(stderr, "\n");
+            }
             if (std::fabs(g[j + 1]) <= c->opt.rtol * bnorm || hcol[j + 1] == 0.0) break;
         }
         // y = H^-1 g (upper triangular), k += Z y

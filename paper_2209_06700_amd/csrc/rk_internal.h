@@ -103,9 +103,10 @@ hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* 
 hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* out,
                             const double* D, int qout, int qin, int N, hipStream_t st);
 
-// out_i = c1[i] G + c2[i] w  (fp64), G may be null.  c1, c2: device doubles.
+// out_i = c1[i] G + c2[i] w on interior nodes, 0 on boundary nodes (fp64, N
+// nodes per direction); G may be null.  c1, c2: device doubles.
 hipError_t launch_rhs_mix(const double* G, const double* w, double* out, const double* c1,
-                          const double* c2, int Q, long long n3, hipStream_t st);
+                          const double* c2, int Q, int N, hipStream_t st);
 
 // Partial dot products: part[blk * nout + l] = sum_{i in blk} X_l[i] * w[i] for
 // l < nvec, and (if self) part[blk * nout + nvec] = sum w[i]^2, nout = nvec + self.
