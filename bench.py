@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--op-reps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--mode", choices=["full", "op"], default="full",
+                    help="op: only the batched fp32 block operator launches (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -141,6 +143,16 @@ def main():
     n, k, Q, tau = args.n, 4, 4, 5e-4
     N = n * k + 1
     log(f"[bench] creating 64^3-class context n={n} k={k} Q={Q}")
+    if args.mode == "op":
+        # explicit Chebyshev bounds: no eigenvalue estimation launches at create
+        solver = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, restart=1,
+                            eig_max=[1.0] * R.n_levels(n))
+        u32 = torch.randn(Q * N ** 3, dtype=torch.float32, device="cuda")
+        v32 = torch.empty_like(u32)
+        t_blk = time_op(torch, R, solver.ctx, R.RK_OP_BLOCKS, u32, v32, args.op_reps)
+        print(json.dumps({"mode": "op", "blocks_fp32_us": t_blk * 1e6, "reps": args.op_reps,
+                          "GBps": 8.0 * Q * N ** 3 / t_blk / 1e9}), flush=True)
+        return 0
     solver = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, rtol=1e-10)
     ctx = solver.ctx
     # operator throughput: batched fp32 block operator, all Q stages per launch

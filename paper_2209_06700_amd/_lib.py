@@ -12,7 +12,8 @@ import os
 import torch  # noqa: F401  (load torch's HIP runtime before the library)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librk.so")
+# RK_LIB_PATH selects another build of the same library (tuning experiments)
+LIB_PATH = os.environ.get("RK_LIB_PATH", os.path.join(HERE, "librk.so"))
 
 RK_OK, RK_EINVAL, RK_EWORKSPACE, RK_EHIP, RK_ENOCONV = 0, -1, -2, -3, -4
 RK_FP64, RK_FP32 = 0, 1

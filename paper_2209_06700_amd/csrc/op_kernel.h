@@ -41,6 +41,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
 #include <utility>
 
 #include "element_data.h"
@@ -76,14 +78,14 @@ template <int K>
 struct Tile {
     static constexpr int CX = (32 / K) > 0 ? (32 / K) : 1;  // elements per tile in x
     static constexpr int TX = CX * K;                       // owned nodes in x
-    static constexpr int CY = 8;                            // pencils per tile in y
+    // pencils per tile in y (taller tiles cut the x-pass halo rows but leave
+    // fewer resident workgroups per CU, which measured slower)
+    static constexpr int CY = 8;
     static constexpr int TY = CY * K;                       // owned nodes in y
     static constexpr int NT = TX * CY;                      // threads
     static constexpr int RX = TX + K + 1;                   // staged input width
     static constexpr int RY = TY + K + 1;                   // staged input height
     static constexpr int XP = TX + 1;                       // padded LDS row of X1/X2
-    static constexpr int CZ = (32 / K) > 0 ? (32 / K) : 1;  // elements per z-chunk
-    static constexpr int TZ = CZ * K;
 };
 
 template <typename T>
@@ -95,6 +97,7 @@ struct OpArgs {
     long long stride;
     int n, s0, nstage, qin;
     int tiles_x, tiles_y, chunks_z, nwork, per_xcd;
+    int cz;                                       // elements per z-chunk
     int xo_zero;
     T ca, cb;
     T alpha[RK_MAX_Q], beta[RK_MAX_Q];            // diagonal mix, per stage
@@ -139,16 +142,24 @@ __device__ __forceinline__ T diag_rt(int r) {
     return d;
 }
 
+#ifndef RK_OP_WAVES_PER_EU
+#define RK_OP_WAVES_PER_EU 1
+#endif
+
 template <int K, typename T, int MIX, int EPI>
-__global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
+__global__ void __launch_bounds__(Tile<K>::NT) __attribute__((amdgpu_waves_per_eu(RK_OP_WAVES_PER_EU)))
+op_kernel(OpArgs<T> p) {
     using TL = Tile<K>;
     constexpr int P = K + 1;
     constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, RX = TL::RX, RY = TL::RY;
-    constexpr int XP = TL::XP, CX = TL::CX, CZ = TL::CZ, TZ = TL::TZ;
+    constexpr int XP = TL::XP, CX = TL::CX;
     constexpr int NU = MIX == MIX_DENSE ? 2 : 1;
-    __shared__ T sU[NU * RY * RX];
-    __shared__ T sX1[RY * XP];
-    __shared__ T sX2[RY * XP];
+    constexpr int NSLOT = (RY * RX + NT - 1) / NT;      // staged values per thread
+    constexpr int NXIT = (RY * CX + NT - 1) / NT;       // x-pass items per thread
+    constexpr int USZ = NU * RY * RX, XSZ = RY * XP;
+    __shared__ T sU[2 * USZ];     // staged input plane, double buffered
+    __shared__ T sX1[2 * XSZ];    // x-pass results, double buffered
+    __shared__ T sX2[2 * XSZ];
 
     const int bid = blockIdx.x;
     const int w = (bid & 7) * p.per_xcd + (bid >> 3);
@@ -164,21 +175,27 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
 
     const int n = p.n, nK = n * K, N = nK + 1;
     const long long NN = (long long)N * N;
+    const int CZ = p.cz;
+    const int TZ = CZ * K;
     const int X0 = itx * TX, Y0 = ity * TY, E0 = icz * CZ, Z0 = E0 * K;
     const int tid = threadIdx.x;
     const int tx = tid % TX, py = tid / TX;
     const int gx = X0 + tx, gy0 = Y0 + py * K;
     // vs may alias p.xo (in-place Chebyshev update), so it is not restrict.
     T* vs = p.v + (long long)s * p.stride;
+    // 32-bit in-plane offset of this thread's first pencil node
+    const unsigned colbase = (unsigned)gy0 * (unsigned)N + (unsigned)gx;
 
     // Tiles that own only far-boundary nodes: write the zeros and leave.
     if (X0 >= nK || Y0 >= nK || Z0 >= nK) {
         const int z1 = min(Z0 + TZ, N);
         if (gx < N)
-            for (int z = Z0; z < z1; ++z)
+            for (int z = Z0; z < z1; ++z) {
+                T* pl = vs + z * NN;
 #pragma unroll
                 for (int a = 0; a < K; ++a)
-                    if (gy0 + a < N) vs[z * NN + (long long)(gy0 + a) * N + gx] = T(0);
+                    if (gy0 + a < N) pl[colbase + (unsigned)(a * N)] = T(0);
+            }
         return;
     }
 
@@ -189,74 +206,119 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
     }
     const T* __restrict__ us = p.u + (long long)s * p.stride;
 
-    T acc[P][K];
-    T sv[K], tv[K];
-
-    // Load one node plane of the tile (+halo), x-pass, y-pass -> sv, tv.
-    auto plane = [&](int z) __attribute__((always_inline)) {
-        if (z <= 0 || z >= nK) {
+    // Load slots of this thread: in-plane offset and validity (interior in x, y).
+    unsigned soff[NSLOT];
+    unsigned smask = 0;
 #pragma unroll
-            for (int a = 0; a < K; ++a) { sv[a] = T(0); tv[a] = T(0); }
-            return;
-        }
-        const long long zoff = (long long)z * NN;
-        for (int i = tid; i < RY * RX; i += NT) {
-            const int r = i / RX, c = i - r * RX;
-            const int xx = X0 - K + c, yy = Y0 - K + r;
-            T val = T(0), val2 = T(0);
-            if (xx > 0 && xx < nK && yy > 0 && yy < nK) {
-                const long long off = zoff + (long long)yy * N + xx;
-                if (MIX == MIX_DIAG) {
-                    val = us[off];
-                } else {
-                    for (int j = 0; j < p.qin; ++j) {
-                        const T uj = p.u[(long long)j * p.stride + off];
-                        val = fma(p.DM[s * RK_MAX_Q + j], uj, val);
-                        val2 = fma(p.DK[s * RK_MAX_Q + j], uj, val2);
+    for (int m = 0; m < NSLOT; ++m) {
+        const int i = tid + m * NT;
+        const int r = i / RX, c = i - r * RX;
+        const int xx = X0 - K + c, yy = Y0 - K + r;
+        const bool ok = i < RY * RX && xx > 0 && xx < nK && yy > 0 && yy < nK;
+        soff[m] = ok ? (unsigned)yy * (unsigned)N + (unsigned)xx : 0u;
+        smask |= ok ? (1u << m) : 0u;
+    }
+    T pre[NU][NSLOT];
+    // Issue the loads of plane z into registers (zeros outside the interior).
+    auto issue = [&](int z) __attribute__((always_inline)) {
+        const bool zin = z > 0 && z < nK;
+        if (MIX == MIX_DIAG) {
+            if (zin) {
+                // every slot loads from a valid address (offset 0 for slots
+                // outside the interior) and selects zero afterwards
+                const T* __restrict__ pl = us + z * NN;
+#pragma unroll
+                for (int m = 0; m < NSLOT; ++m) {
+                    const T vv = pl[soff[m]];
+                    pre[0][m] = (smask >> m & 1u) ? vv : T(0);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < NSLOT; ++m) pre[0][m] = T(0);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < NSLOT; ++m) { pre[0][m] = T(0); pre[1][m] = T(0); }
+            if (zin) {
+                for (int j = 0; j < p.qin; ++j) {
+                    const T* __restrict__ pl = p.u + (long long)j * p.stride + z * NN;
+                    const T dm = p.DM[s * RK_MAX_Q + j], dk = p.DK[s * RK_MAX_Q + j];
+#pragma unroll
+                    for (int m = 0; m < NSLOT; ++m) {
+                        const T lv = pl[soff[m]];
+                        const T uj = (smask >> m & 1u) ? lv : T(0);
+                        pre[0][m] = fma(dm, uj, pre[0][m]);
+                        pre[1][m] = fma(dk, uj, pre[1][m]);
                     }
                 }
             }
-            sU[i] = val;
-            if (MIX == MIX_DENSE) sU[RY * RX + i] = val2;
         }
-        __syncthreads();
-        for (int it = tid; it < RY * CX; it += NT) {
-            const int cx = it / RY, r = it - cx * RY;
-            T wv[2 * K + 1], mx[K], kx[K];
-            const T* src = &sU[r * RX + cx * K];
+    };
+    auto commit = [&](int buf) __attribute__((always_inline)) {
+        T* dst = sU + buf * USZ;
 #pragma unroll
-            for (int j = 0; j <= 2 * K; ++j) wv[j] = src[j];
-            T* o1 = &sX1[r * XP + cx * K];
-            T* o2 = &sX2[r * XP + cx * K];
-            if (MIX == MIX_DIAG) {
-                row_apply<K, 0, T>(wv, mx);
-                row_apply<K, 1, T>(wv, kx);
+        for (int m = 0; m < NSLOT; ++m) {
+            const int i = tid + m * NT;
+            if (m < NSLOT - 1 || i < RY * RX) {
+                dst[i] = pre[0][m];
+                if (MIX == MIX_DENSE) dst[RY * RX + i] = pre[1][m];
+            }
+        }
+    };
+
+    T acc[P][K];
+    T sv[K], tv[K];
+
+    // x-pass of the plane staged in sU[buf] -> sX1/sX2[buf]
+    auto xpass = [&](int buf) __attribute__((always_inline)) {
+        const T* U = sU + buf * USZ;
+        T* X1 = sX1 + buf * XSZ;
+        T* X2 = sX2 + buf * XSZ;
 #pragma unroll
-                for (int a = 0; a < K; ++a) {
-                    o1[a] = fma(alpha, mx[a], beta * kx[a]);
-                    o2[a] = beta * mx[a];
-                }
-            } else {
-                T wk[2 * K + 1], mk[K];
-                const T* src2 = src + RY * RX;
+        for (int q = 0; q < NXIT; ++q) {
+            const int it = tid + q * NT;
+            if (q < NXIT - 1 || it < RY * CX) {
+                const int cx = it / RY, r = it - cx * RY;
+                T wv[2 * K + 1], mx[K], kx[K];
+                const T* src = &U[r * RX + cx * K];
 #pragma unroll
-                for (int j = 0; j <= 2 * K; ++j) wk[j] = src2[j];
-                row_apply<K, 0, T>(wv, mx);
-                row_apply<K, 1, T>(wk, kx);
-                row_apply<K, 0, T>(wk, mk);
+                for (int j = 0; j <= 2 * K; ++j) wv[j] = src[j];
+                T* o1 = &X1[r * XP + cx * K];
+                T* o2 = &X2[r * XP + cx * K];
+                if (MIX == MIX_DIAG) {
+                    row_apply<K, 0, T>(wv, mx);
+                    row_apply<K, 1, T>(wv, kx);
 #pragma unroll
-                for (int a = 0; a < K; ++a) {
-                    o1[a] = mx[a] + kx[a];
-                    o2[a] = mk[a];
+                    for (int a = 0; a < K; ++a) {
+                        o1[a] = fma(alpha, mx[a], beta * kx[a]);
+                        o2[a] = beta * mx[a];
+                    }
+                } else {
+                    T wk[2 * K + 1], mk[K];
+                    const T* src2 = src + RY * RX;
+#pragma unroll
+                    for (int j = 0; j <= 2 * K; ++j) wk[j] = src2[j];
+                    row_apply<K, 0, T>(wv, mx);
+                    row_apply<K, 1, T>(wk, kx);
+                    row_apply<K, 0, T>(wk, mk);
+#pragma unroll
+                    for (int a = 0; a < K; ++a) {
+                        o1[a] = mx[a] + kx[a];
+                        o2[a] = mk[a];
+                    }
                 }
             }
         }
-        __syncthreads();
+    };
+    // y-pass of sX1/sX2[buf] for this thread's pencil -> sv, tv
+    auto ypass = [&](int buf) __attribute__((always_inline)) {
+        const T* X1 = sX1 + buf * XSZ;
+        const T* X2 = sX2 + buf * XSZ;
         T w1[2 * K + 1], w2[2 * K + 1], m1[K], k2[K];
 #pragma unroll
         for (int j = 0; j <= 2 * K; ++j) {
-            w1[j] = sX1[(py * K + j) * XP + tx];
-            w2[j] = sX2[(py * K + j) * XP + tx];
+            w1[j] = X1[(py * K + j) * XP + tx];
+            w2[j] = X2[(py * K + j) * XP + tx];
         }
         row_apply<K, 0, T>(w1, m1);
         row_apply<K, 1, T>(w2, k2);
@@ -285,7 +347,9 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
         });
     };
 
-    // Per-thread constants for the epilogue.
+    // Epilogue data.  Boundary status of the thread's nodes in x and y.
+    const bool colok = gx < N;
+    const bool xbnd = gx == 0 || gx == nK;
     T dmx = T(0), dkx = T(0);
     if (EPI == EPI_CHEB) {
         const int rx = gx % K;
@@ -295,68 +359,139 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
     const T* __restrict__ bs = (EPI != EPI_STORE) ? p.b + (long long)s * p.stride : nullptr;
     const T* xos = (EPI == EPI_CHEB && !p.xo_zero) ? p.xo + (long long)s * p.stride : nullptr;
 
+    // Pencils whose nodes are all interior in x and y take the branch-free path.
+    const bool pencil_inner = colok && !xbnd && gy0 > 0 && gy0 + K - 1 < nK;
+    // Write the K completed output planes of element e.
     auto flush = [&](int e) __attribute__((always_inline)) {
-        if (gx >= N) return;
+        if (pencil_inner && e > 0) {
+            cfor<K>([&](auto cm) {
+                constexpr int c = decltype(cm)::value;
+                const long long zo = (long long)(e * K + c) * NN;
+                cfor<K>([&](auto am) {
+                    constexpr int a = decltype(am)::value;
+                    const long long ro = zo + (long long)a * N;     // uniform row offset
+                    const T av = acc[c][a];
+                    T out;
+                    if (EPI == EPI_STORE) {
+                        out = av;
+                    } else if (EPI == EPI_RESID) {
+                        out = bs[ro + colbase] - av;
+                    } else {
+                        constexpr T dmy = T(DG<K, 0, a>::v), dky = T(DG<K, 1, a>::v);
+                        constexpr T dmz = T(DG<K, 0, c>::v), dkz = T(DG<K, 1, c>::v);
+                        const T dM = dmx * (dmy * dmz);
+                        const T dK = dkx * (dmy * dmz) + dmx * (dky * dmz + dmy * dkz);
+                        const T D = fma(alpha, dM, beta * dK);
+                        const T x = us[ro + colbase];
+                        const T xo = xos ? xos[ro + colbase] : T(0);
+                        out = x + p.ca * (x - xo) + p.cb * (bs[ro + colbase] - av) / D;
+                    }
+                    (vs + ro)[colbase] = out;
+                });
+            });
+            return;
+        }
+        if (!colok) return;
         cfor<K>([&](auto cm) {
             constexpr int c = decltype(cm)::value;
             const int z = e * K + c;
+            const long long zo = (long long)z * NN;
+            T* vpl = vs + zo;
+            const bool zb = z == 0;
             cfor<K>([&](auto am) {
                 constexpr int a = decltype(am)::value;
                 const int y = gy0 + a;
                 if (y < N) {
-                    const long long off = (long long)z * NN + (long long)y * N + gx;
-                    const bool bnd = gx == 0 || gx == nK || y == 0 || y == nK || z == 0;
+                    const unsigned off = colbase + (unsigned)(a * N);
+                    const bool bnd = zb || xbnd || y == 0 || y == nK;
                     T out = T(0);
                     if (!bnd) {
                         const T av = acc[c][a];
                         if (EPI == EPI_STORE) {
                             out = av;
                         } else if (EPI == EPI_RESID) {
-                            out = bs[off] - av;
+                            out = bs[zo + off] - av;
                         } else {
                             constexpr T dmy = T(DG<K, 0, a>::v), dky = T(DG<K, 1, a>::v);
                             constexpr T dmz = T(DG<K, 0, c>::v), dkz = T(DG<K, 1, c>::v);
                             const T dM = dmx * (dmy * dmz);
                             const T dK = dkx * (dmy * dmz) + dmx * (dky * dmz + dmy * dkz);
                             const T D = fma(alpha, dM, beta * dK);
-                            const T x = us[off];
-                            const T xo = xos ? xos[off] : T(0);
-                            out = x + p.ca * (x - xo) + p.cb * (bs[off] - av) / D;
+                            const T x = us[zo + off];
+                            const T xo = xos ? xos[zo + off] : T(0);
+                            out = x + p.ca * (x - xo) + p.cb * (bs[zo + off] - av) / D;
                         }
                     }
-                    vs[off] = out;
+                    vpl[off] = out;
                 }
             });
         });
     };
 
-    const int E1 = min(E0 + CZ, n);
-    const int ebeg = E0 > 0 ? E0 - 1 : 0;
-    plane(ebeg * K);
-    zinit();
-    for (int e = ebeg; e < E1; ++e) {
-#pragma unroll 1
-        for (int b = 1; b <= K; ++b) {
-            plane(e * K + b);
+    // z-accumulation of the plane just y-passed (plane index b within the
+    // current element e); flush when the element's top plane has arrived.
+    int e = 0, b = 0;
+    auto zstep = [&](bool first) __attribute__((always_inline)) {
+        if (first) {
+            zinit();
+        } else {
             cfor<K>([&](auto bm) {
                 constexpr int B = decltype(bm)::value + 1;
                 if (b == B) zacc(std::integral_constant<int, B>{});
             });
         }
-        if (e >= E0) flush(e);
-        // The top plane of element e is the bottom plane of element e+1.
-        T carry[K];
+        if (b == K) {
+            if (e >= E0) flush(e);
+            // the top plane of element e is the bottom plane of element e+1
+            T carry[K];
 #pragma unroll
-        for (int a = 0; a < K; ++a) carry[a] = acc[K][a];
-        zinit();
+            for (int a = 0; a < K; ++a) carry[a] = acc[K][a];
+            zinit();
 #pragma unroll
-        for (int a = 0; a < K; ++a) acc[0][a] += carry[a];
+            for (int a = 0; a < K; ++a) acc[0][a] += carry[a];
+            ++e;
+            b = 0;
+        }
+        ++b;
+    };
+
+    // March up the chunk over the planes zbeg .. zend, each processed once.
+    // Iteration q: y-pass + z-accumulation of plane q-1, x-pass of plane q,
+    // staging of plane q+1 (loaded during iteration q-1), loads of plane q+2;
+    // then one barrier.  The three phases use disjoint LDS buffers.
+    const int E1 = min(E0 + CZ, n);
+    const int ebeg = E0 > 0 ? E0 - 1 : 0;
+    const int zbeg = ebeg * K, zend = E1 * K;
+    const int NP = zend - zbeg + 1;
+    e = ebeg;
+    issue(zbeg);
+    commit(0);
+    if (NP > 1) issue(zbeg + 1);
+    __syncthreads();
+    xpass(0);
+    if (NP > 1) {
+        commit(1);
+        if (NP > 2) issue(zbeg + 2);
     }
+    __syncthreads();
+    for (int q = 1; q < NP; ++q) {
+        ypass((q - 1) & 1);
+        zstep(q == 1);
+        xpass(q & 1);
+        if (q + 1 < NP) {
+            commit((q + 1) & 1);
+            if (q + 2 < NP) issue(zbeg + q + 2);
+        }
+        __syncthreads();
+    }
+    ypass((NP - 1) & 1);
+    zstep(NP == 1);
     // The chunk that contains the top boundary plane writes it.
-    if (E0 + CZ > n && gx < N) {
+    if (E0 + CZ > n && colok) {
+        T* pl = vs + (long long)nK * NN;
 #pragma unroll
         for (int a = 0; a < K; ++a)
-            if (gy0 + a < N) vs[(long long)nK * NN + (long long)(gy0 + a) * N + gx] = T(0);
+            if (gy0 + a < N) pl[colbase + (unsigned)(a * N)] = T(0);
     }
 }
 
@@ -376,7 +511,13 @@ hipError_t launch_op_typed(const OpLaunch& L) {
     const int N = L.n * K + 1;
     p.tiles_x = (N + TL::TX - 1) / TL::TX;
     p.tiles_y = (N + TL::TY - 1) / TL::TY;
-    p.chunks_z = (N + TL::TZ - 1) / TL::TZ;
+    // z-chunk length: long enough to amortise the k re-read planes, short
+    // enough to give every CU several workgroups
+    int cz = 16;
+    while (cz > 2 && (long long)p.tiles_x * p.tiles_y * ((L.n + cz - 1) / cz) * L.nstage < 2048) cz /= 2;
+    if (const char* env = std::getenv("RK_OP_CZ")) cz = std::max(1, std::atoi(env));   // tuning override
+    p.cz = cz;
+    p.chunks_z = (N + cz * K - 1) / (cz * K);
     p.nwork = p.tiles_x * p.tiles_y * p.chunks_z * L.nstage;
     p.per_xcd = (p.nwork + 7) / 8;
     p.xo_zero = L.xo == nullptr;
