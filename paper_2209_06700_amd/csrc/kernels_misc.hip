@@ -191,7 +191,8 @@ __global__ void __launch_bounds__(kBlock) cheb_first_kernel(Scal<T> sc, int k,
 template <typename Tin, typename Tout>
 __global__ void __launch_bounds__(kBlock) stage_mix_kernel(const Tin* __restrict__ in, Tout* __restrict__ out,
                                                            const double* __restrict__ D, int qout,
-                                                           int qin, int N) {
+                                                           int qin, int N, double* __restrict__ out2,
+                                                           const double* __restrict__ D2) {
     const int nK = N - 1;
     const long long N3 = (long long)N * N * N;
     for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N3;
@@ -206,11 +207,15 @@ __global__ void __launch_bounds__(kBlock) stage_mix_kernel(const Tin* __restrict
 #pragma unroll
         for (int i = 0; i < RK_MAX_Q; ++i) {
             if (i >= qout) break;
-            double acc = 0.0;
+            double acc = 0.0, acc2 = 0.0;
 #pragma unroll
             for (int j = 0; j < RK_MAX_Q; ++j)
-                if (j < qin) acc = fma(D[i * qin + j], u[j], acc);
+                if (j < qin) {
+                    acc = fma(D[i * qin + j], u[j], acc);
+                    if (out2) acc2 = fma(D2[i * qin + j], u[j], acc2);
+                }
             out[(long long)i * N3 + r] = (Tout)acc;
+            if (out2) out2[(long long)i * N3 + r] = acc2;
         }
     }
 }
@@ -480,17 +485,17 @@ hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* 
 }
 
 hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* out, const double* D,
-                            int qout, int qin, int N, hipStream_t st) {
+                            int qout, int qin, int N, hipStream_t st, double* out2, const double* D2) {
     const long long N3 = (long long)N * N * N;
     dim3 g(grid_for(N3)), b(kBlock);
     if (dtype_in == RK_FP64 && dtype_out == RK_FP64)
-        stage_mix_kernel<double, double><<<g, b, 0, st>>>((const double*)in, (double*)out, D, qout, qin, N);
+        stage_mix_kernel<double, double><<<g, b, 0, st>>>((const double*)in, (double*)out, D, qout, qin, N, out2, D2);
     else if (dtype_in == RK_FP64 && dtype_out == RK_FP32)
-        stage_mix_kernel<double, float><<<g, b, 0, st>>>((const double*)in, (float*)out, D, qout, qin, N);
+        stage_mix_kernel<double, float><<<g, b, 0, st>>>((const double*)in, (float*)out, D, qout, qin, N, out2, D2);
     else if (dtype_in == RK_FP32 && dtype_out == RK_FP64)
-        stage_mix_kernel<float, double><<<g, b, 0, st>>>((const float*)in, (double*)out, D, qout, qin, N);
+        stage_mix_kernel<float, double><<<g, b, 0, st>>>((const float*)in, (double*)out, D, qout, qin, N, out2, D2);
     else
-        stage_mix_kernel<float, float><<<g, b, 0, st>>>((const float*)in, (float*)out, D, qout, qin, N);
+        stage_mix_kernel<float, float><<<g, b, 0, st>>>((const float*)in, (float*)out, D, qout, qin, N, out2, D2);
     return hipGetLastError();
 }
 

@@ -10,13 +10,28 @@
 // one banded 1D product per direction and term, with no element gather/scatter
 // and no write conflicts (every output node is owned by exactly one thread).
 //
+// Operator for output stage s (per-stage scales in the kernel arguments, 1D
+// element matrices as compile-time constants, cell size folded into scales):
+//   diagonal mix:  v_s = alpha_s Mref u_s  + beta_s Kref u_s
+//   pair mix:      v_s = alpha_s Mref uM_s + beta_s Kref uK_s
+// with Mref = Mhat (x) Mhat (x) Mhat and Kref the matching stiffness sum.  The
+// pair form takes two input vectors; the Q x Q stage mixes of the dense
+// operators (A^-1 (x) M, A (x) K) are applied to the inputs by a streaming
+// kernel beforehand, so this kernel never reads more than two inputs per node.
+//
+// Sum factorisation (per node plane), wM / wK the mass / stiffness inputs:
+//   X1 = alpha Mhat_x wM + beta Khat_x wK,  X2 = beta Mhat_x wK   (x-pass)
+//   S  = Mhat_y X1 + Khat_y X2,             T  = Mhat_y X2          (y-pass)
+//   v  = Mhat_z S + Khat_z T                                       (z)
+//
 // Work decomposition (one workgroup):
 //   * an x-y tile of TX x TY output nodes (element aligned) and a z-chunk of
-//     CZ elements; all Q stages of one tile are consecutive workgroups on one
-//     XCD so that the dense stage mix re-reads inputs from that XCD's L2;
+//     cz elements; all Q stages of one tile are consecutive workgroups on one
+//     XCD (shared halo reads in that XCD's L2);
 //   * the workgroup marches up the z-chunk one node plane at a time:
 //       1. the input plane tile plus a halo of k nodes below and 1 above in x
-//          and y is staged in LDS (zero outside the interior: Dirichlet);
+//          and y is staged in LDS (zero outside the interior: Dirichlet); the
+//          loads of a plane are issued ahead, into registers;
 //       2. x-pass: every (row, x-element) item applies the 1D matrices to the
 //          2k+1 inputs it needs and writes k outputs to LDS;
 //       3. y-pass: every thread owns one x column and a y-pencil of k nodes
@@ -25,18 +40,11 @@
 //          per-thread registers per pencil node; when an element's top plane
 //          has been added, k output planes are complete and are written (with
 //          the epilogue: store, residual or Chebyshev update).
-//   The z-chunk re-reads the k planes of the element below it.
-//
-// Operator for output stage s (per-stage scalars in the kernel arguments,
-// 1D element matrices as compile-time constants):
-//   diagonal mix:  v_s = alpha_s Mref u_s + beta_s Kref u_s
-//   dense mix:     v_s = Mref (sum_j DM[s][j] u_j) + Kref (sum_j DK[s][j] u_j)
-// with Mref = Mhat (x) Mhat (x) Mhat etc. (cell size folded into the scales).
-// Sum factorisation used (per plane): with wM, wK the two mixed inputs,
-//   X1 = Mhat_x wM + Khat_x wK,  X2 = Mhat_x wK          (x-pass)
-//   S  = Mhat_y X1 + Khat_y X2,  T  = Mhat_y X2           (y-pass)
-//   v  = Mhat_z S + Khat_z T                              (z accumulation)
-// which expands to Mref wM + Kref wK.
+//   With double-buffered LDS (fp32) one iteration does the y-pass of plane
+//   q-1, the x-pass of plane q and the staging of plane q+1 behind a single
+//   barrier; fp64 keeps single buffers (half the LDS, more resident
+//   workgroups) and two barriers.  The z-chunk re-reads the k planes of the
+//   element below it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -90,18 +98,18 @@ struct Tile {
 
 template <typename T>
 struct OpArgs {
-    const T* u;
+    const T* u;       // input (both terms for the diagonal mix; mass term for the pair)
+    const T* u2;      // pair mix: stiffness-term input
     T* v;
     const T* b;
     const T* xo;
     long long stride;
-    int n, s0, nstage, qin;
+    int n, s0, nstage;
     int tiles_x, tiles_y, chunks_z, nwork, per_xcd;
     int cz;                                       // elements per z-chunk
     int xo_zero;
     T ca, cb;
-    T alpha[RK_MAX_Q], beta[RK_MAX_Q];            // diagonal mix, per stage
-    T DM[RK_MAX_Q * RK_MAX_Q], DK[RK_MAX_Q * RK_MAX_Q];   // dense mix
+    T alpha[RK_MAX_Q], beta[RK_MAX_Q];            // per-stage scales
 };
 
 // out[a] = (E w)[a] for the k nodes eK..eK+k-1 of element e, where
@@ -142,24 +150,20 @@ __device__ __forceinline__ T diag_rt(int r) {
     return d;
 }
 
-#ifndef RK_OP_WAVES_PER_EU
-#define RK_OP_WAVES_PER_EU 1
-#endif
-
 template <int K, typename T, int MIX, int EPI>
-__global__ void __launch_bounds__(Tile<K>::NT) __attribute__((amdgpu_waves_per_eu(RK_OP_WAVES_PER_EU)))
-op_kernel(OpArgs<T> p) {
+__global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
     using TL = Tile<K>;
     constexpr int P = K + 1;
     constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, RX = TL::RX, RY = TL::RY;
     constexpr int XP = TL::XP, CX = TL::CX;
-    constexpr int NU = MIX == MIX_DENSE ? 2 : 1;
+    constexpr int NU = MIX == MIX_PAIR ? 2 : 1;
+    constexpr int NBUF = sizeof(T) == 4 ? 2 : 1;          // LDS buffers per array
     constexpr int NSLOT = (RY * RX + NT - 1) / NT;      // staged values per thread
     constexpr int NXIT = (RY * CX + NT - 1) / NT;       // x-pass items per thread
     constexpr int USZ = NU * RY * RX, XSZ = RY * XP;
-    __shared__ T sU[2 * USZ];     // staged input plane, double buffered
-    __shared__ T sX1[2 * XSZ];    // x-pass results, double buffered
-    __shared__ T sX2[2 * XSZ];
+    __shared__ T sU[NBUF * USZ];
+    __shared__ T sX1[NBUF * XSZ];
+    __shared__ T sX2[NBUF * XSZ];
 
     const int bid = blockIdx.x;
     const int w = (bid & 7) * p.per_xcd + (bid >> 3);
@@ -199,12 +203,10 @@ op_kernel(OpArgs<T> p) {
         return;
     }
 
-    T alpha = T(0), beta = T(0);
-    if (MIX == MIX_DIAG) {
-        alpha = p.alpha[s];
-        beta = p.beta[s];
-    }
+    const T alpha = p.alpha[s];
+    const T beta = p.beta[s];
     const T* __restrict__ us = p.u + (long long)s * p.stride;
+    const T* __restrict__ us2 = MIX == MIX_PAIR ? p.u2 + (long long)s * p.stride : nullptr;
 
     // Load slots of this thread: in-plane offset and validity (interior in x, y).
     unsigned soff[NSLOT];
@@ -220,38 +222,29 @@ op_kernel(OpArgs<T> p) {
     }
     T pre[NU][NSLOT];
     // Issue the loads of plane z into registers (zeros outside the interior).
+    // Every slot loads from a valid address (offset 0 for slots outside the
+    // interior) and selects zero afterwards.
     auto issue = [&](int z) __attribute__((always_inline)) {
-        const bool zin = z > 0 && z < nK;
-        if (MIX == MIX_DIAG) {
-            if (zin) {
-                // every slot loads from a valid address (offset 0 for slots
-                // outside the interior) and selects zero afterwards
-                const T* __restrict__ pl = us + z * NN;
+        if (z > 0 && z < nK) {
+            const T* __restrict__ pl = us + z * NN;
+#pragma unroll
+            for (int m = 0; m < NSLOT; ++m) {
+                const T vv = pl[soff[m]];
+                pre[0][m] = (smask >> m & 1u) ? vv : T(0);
+            }
+            if (MIX == MIX_PAIR) {
+                const T* __restrict__ pl2 = us2 + z * NN;
 #pragma unroll
                 for (int m = 0; m < NSLOT; ++m) {
-                    const T vv = pl[soff[m]];
-                    pre[0][m] = (smask >> m & 1u) ? vv : T(0);
+                    const T vv = pl2[soff[m]];
+                    pre[NU - 1][m] = (smask >> m & 1u) ? vv : T(0);
                 }
-            } else {
-#pragma unroll
-                for (int m = 0; m < NSLOT; ++m) pre[0][m] = T(0);
             }
         } else {
 #pragma unroll
-            for (int m = 0; m < NSLOT; ++m) { pre[0][m] = T(0); pre[1][m] = T(0); }
-            if (zin) {
-                for (int j = 0; j < p.qin; ++j) {
-                    const T* __restrict__ pl = p.u + (long long)j * p.stride + z * NN;
-                    const T dm = p.DM[s * RK_MAX_Q + j], dk = p.DK[s * RK_MAX_Q + j];
+            for (int m = 0; m < NSLOT; ++m)
 #pragma unroll
-                    for (int m = 0; m < NSLOT; ++m) {
-                        const T lv = pl[soff[m]];
-                        const T uj = (smask >> m & 1u) ? lv : T(0);
-                        pre[0][m] = fma(dm, uj, pre[0][m]);
-                        pre[1][m] = fma(dk, uj, pre[1][m]);
-                    }
-                }
-            }
+                for (int j = 0; j < NU; ++j) pre[j][m] = T(0);
         }
     };
     auto commit = [&](int buf) __attribute__((always_inline)) {
@@ -261,7 +254,7 @@ op_kernel(OpArgs<T> p) {
             const int i = tid + m * NT;
             if (m < NSLOT - 1 || i < RY * RX) {
                 dst[i] = pre[0][m];
-                if (MIX == MIX_DENSE) dst[RY * RX + i] = pre[1][m];
+                if (MIX == MIX_PAIR) dst[RY * RX + i] = pre[NU - 1][m];
             }
         }
     };
@@ -303,8 +296,8 @@ op_kernel(OpArgs<T> p) {
                     row_apply<K, 0, T>(wk, mk);
 #pragma unroll
                     for (int a = 0; a < K; ++a) {
-                        o1[a] = mx[a] + kx[a];
-                        o2[a] = mk[a];
+                        o1[a] = fma(alpha, mx[a], beta * kx[a]);
+                        o2[a] = beta * mk[a];
                     }
                 }
             }
@@ -359,6 +352,23 @@ op_kernel(OpArgs<T> p) {
     const T* __restrict__ bs = (EPI != EPI_STORE) ? p.b + (long long)s * p.stride : nullptr;
     const T* xos = (EPI == EPI_CHEB && !p.xo_zero) ? p.xo + (long long)s * p.stride : nullptr;
 
+    // value written at an interior node (c, a) of the completed element
+    auto epi_value = [&](auto cm, auto am, long long gofs) __attribute__((always_inline)) {
+        constexpr int c = decltype(cm)::value;
+        constexpr int a = decltype(am)::value;
+        const T av = acc[c][a];
+        if (EPI == EPI_STORE) return av;
+        if (EPI == EPI_RESID) return bs[gofs] - av;
+        constexpr T dmy = T(DG<K, 0, a>::v), dky = T(DG<K, 1, a>::v);
+        constexpr T dmz = T(DG<K, 0, c>::v), dkz = T(DG<K, 1, c>::v);
+        const T dM = dmx * (dmy * dmz);
+        const T dK = dkx * (dmy * dmz) + dmx * (dky * dmz + dmy * dkz);
+        const T D = fma(alpha, dM, beta * dK);
+        const T x = us[gofs];
+        const T xo = xos ? xos[gofs] : T(0);
+        return x + p.ca * (x - xo) + p.cb * (bs[gofs] - av) / D;
+    };
+
     // Pencils whose nodes are all interior in x and y take the branch-free path.
     const bool pencil_inner = colok && !xbnd && gy0 > 0 && gy0 + K - 1 < nK;
     // Write the K completed output planes of element e.
@@ -370,23 +380,7 @@ op_kernel(OpArgs<T> p) {
                 cfor<K>([&](auto am) {
                     constexpr int a = decltype(am)::value;
                     const long long ro = zo + (long long)a * N;     // uniform row offset
-                    const T av = acc[c][a];
-                    T out;
-                    if (EPI == EPI_STORE) {
-                        out = av;
-                    } else if (EPI == EPI_RESID) {
-                        out = bs[ro + colbase] - av;
-                    } else {
-                        constexpr T dmy = T(DG<K, 0, a>::v), dky = T(DG<K, 1, a>::v);
-                        constexpr T dmz = T(DG<K, 0, c>::v), dkz = T(DG<K, 1, c>::v);
-                        const T dM = dmx * (dmy * dmz);
-                        const T dK = dkx * (dmy * dmz) + dmx * (dky * dmz + dmy * dkz);
-                        const T D = fma(alpha, dM, beta * dK);
-                        const T x = us[ro + colbase];
-                        const T xo = xos ? xos[ro + colbase] : T(0);
-                        out = x + p.ca * (x - xo) + p.cb * (bs[ro + colbase] - av) / D;
-                    }
-                    (vs + ro)[colbase] = out;
+                    (vs + ro)[colbase] = epi_value(cm, am, ro + colbase);
                 });
             });
             return;
@@ -396,33 +390,13 @@ op_kernel(OpArgs<T> p) {
             constexpr int c = decltype(cm)::value;
             const int z = e * K + c;
             const long long zo = (long long)z * NN;
-            T* vpl = vs + zo;
-            const bool zb = z == 0;
             cfor<K>([&](auto am) {
                 constexpr int a = decltype(am)::value;
                 const int y = gy0 + a;
                 if (y < N) {
                     const unsigned off = colbase + (unsigned)(a * N);
-                    const bool bnd = zb || xbnd || y == 0 || y == nK;
-                    T out = T(0);
-                    if (!bnd) {
-                        const T av = acc[c][a];
-                        if (EPI == EPI_STORE) {
-                            out = av;
-                        } else if (EPI == EPI_RESID) {
-                            out = bs[zo + off] - av;
-                        } else {
-                            constexpr T dmy = T(DG<K, 0, a>::v), dky = T(DG<K, 1, a>::v);
-                            constexpr T dmz = T(DG<K, 0, c>::v), dkz = T(DG<K, 1, c>::v);
-                            const T dM = dmx * (dmy * dmz);
-                            const T dK = dkx * (dmy * dmz) + dmx * (dky * dmz + dmy * dkz);
-                            const T D = fma(alpha, dM, beta * dK);
-                            const T x = us[zo + off];
-                            const T xo = xos ? xos[zo + off] : T(0);
-                            out = x + p.ca * (x - xo) + p.cb * (bs[zo + off] - av) / D;
-                        }
-                    }
-                    vpl[off] = out;
+                    const bool bnd = z == 0 || xbnd || y == 0 || y == nK;
+                    (vs + zo)[off] = bnd ? T(0) : epi_value(cm, am, zo + off);
                 }
             });
         });
@@ -456,36 +430,56 @@ op_kernel(OpArgs<T> p) {
     };
 
     // March up the chunk over the planes zbeg .. zend, each processed once.
-    // Iteration q: y-pass + z-accumulation of plane q-1, x-pass of plane q,
-    // staging of plane q+1 (loaded during iteration q-1), loads of plane q+2;
-    // then one barrier.  The three phases use disjoint LDS buffers.
     const int E1 = min(E0 + CZ, n);
     const int ebeg = E0 > 0 ? E0 - 1 : 0;
     const int zbeg = ebeg * K, zend = E1 * K;
     const int NP = zend - zbeg + 1;
     e = ebeg;
-    issue(zbeg);
-    commit(0);
-    if (NP > 1) issue(zbeg + 1);
-    __syncthreads();
-    xpass(0);
-    if (NP > 1) {
-        commit(1);
-        if (NP > 2) issue(zbeg + 2);
-    }
-    __syncthreads();
-    for (int q = 1; q < NP; ++q) {
-        ypass((q - 1) & 1);
-        zstep(q == 1);
-        xpass(q & 1);
-        if (q + 1 < NP) {
-            commit((q + 1) & 1);
-            if (q + 2 < NP) issue(zbeg + q + 2);
+    if (NBUF == 2) {
+        // Iteration q: y-pass + z-accumulation of plane q-1, x-pass of plane
+        // q, staging of plane q+1 (loaded during iteration q-1), loads of
+        // plane q+2; then one barrier.  The phases use disjoint buffers.
+        issue(zbeg);
+        commit(0);
+        if (NP > 1) issue(zbeg + 1);
+        __syncthreads();
+        xpass(0);
+        if (NP > 1) {
+            commit(1);
+            if (NP > 2) issue(zbeg + 2);
         }
         __syncthreads();
+        for (int q = 1; q < NP; ++q) {
+            ypass((q - 1) & 1);
+            zstep(q == 1);
+            xpass(q & 1);
+            if (q + 1 < NP) {
+                commit((q + 1) & 1);
+                if (q + 2 < NP) issue(zbeg + q + 2);
+            }
+            __syncthreads();
+        }
+        ypass((NP - 1) & 1);
+        zstep(NP == 1);
+    } else {
+        // Iteration q: stage plane q (loaded during iteration q-1), loads of
+        // plane q+1, y-pass + z-accumulation of plane q-1; barrier; x-pass of
+        // plane q; barrier.
+        issue(zbeg);
+        for (int q = 0; q < NP; ++q) {
+            commit(0);
+            if (q + 1 < NP) issue(zbeg + q + 1);
+            if (q > 0) {
+                ypass(0);
+                zstep(q == 1);
+            }
+            __syncthreads();
+            xpass(0);
+            __syncthreads();
+        }
+        ypass(0);
+        zstep(NP == 1);
     }
-    ypass((NP - 1) & 1);
-    zstep(NP == 1);
     // The chunk that contains the top boundary plane writes it.
     if (E0 + CZ > n && colok) {
         T* pl = vs + (long long)nK * NN;
@@ -500,6 +494,7 @@ hipError_t launch_op_typed(const OpLaunch& L) {
     using TL = Tile<K>;
     OpArgs<T> p;
     p.u = static_cast<const T*>(L.u);
+    p.u2 = static_cast<const T*>(L.u2);
     p.v = static_cast<T*>(L.v);
     p.b = static_cast<const T*>(L.b);
     p.xo = static_cast<const T*>(L.xo);
@@ -507,7 +502,6 @@ hipError_t launch_op_typed(const OpLaunch& L) {
     p.n = L.n;
     p.s0 = L.s0;
     p.nstage = L.nstage;
-    p.qin = L.qin;
     const int N = L.n * K + 1;
     p.tiles_x = (N + TL::TX - 1) / TL::TX;
     p.tiles_y = (N + TL::TY - 1) / TL::TY;
@@ -527,10 +521,6 @@ hipError_t launch_op_typed(const OpLaunch& L) {
         p.alpha[i] = T(L.alpha[i]);
         p.beta[i] = T(L.beta[i]);
     }
-    for (int i = 0; i < RK_MAX_Q * RK_MAX_Q; ++i) {
-        p.DM[i] = T(L.DM[i]);
-        p.DK[i] = T(L.DK[i]);
-    }
     dim3 grid(8 * p.per_xcd), block(TL::NT);
 #define RK_OP_CASE(MX, EP)                                                      \
     if (L.mix == MX && L.epi == EP) {                                           \
@@ -540,8 +530,8 @@ hipError_t launch_op_typed(const OpLaunch& L) {
     RK_OP_CASE(MIX_DIAG, EPI_STORE)
     RK_OP_CASE(MIX_DIAG, EPI_RESID)
     RK_OP_CASE(MIX_DIAG, EPI_CHEB)
-    RK_OP_CASE(MIX_DENSE, EPI_STORE)
-    RK_OP_CASE(MIX_DENSE, EPI_RESID)
+    RK_OP_CASE(MIX_PAIR, EPI_STORE)
+    RK_OP_CASE(MIX_PAIR, EPI_RESID)
 #undef RK_OP_CASE
     return hipErrorInvalidValue;
 }

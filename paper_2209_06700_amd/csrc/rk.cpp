@@ -43,6 +43,8 @@ hipError_t launch_op(const OpLaunch& L) {
 namespace {
 
 constexpr int kRedBlocks = 1024;     // blocks of the reduction kernels
+// slots (x 81 doubles) of the device Q x Q mixing data
+constexpr int kMixSinv = 0, kMixS = 81, kMixRhs = 162, kMixAinvS = 243, kMixAinv = 324, kMixA = 405;
 constexpr size_t kAlign = 256;
 
 enum Form { F_CALA = 0, F_STAGE = 1, F_BLOCKS = 2, F_K = 3, F_M = 4, F_NFORMS = 5 };
@@ -50,8 +52,8 @@ enum Form { F_CALA = 0, F_STAGE = 1, F_BLOCKS = 2, F_K = 3, F_M = 4, F_NFORMS = 
 // Mixing coefficients of one operator form (cell size folded in).
 struct Coeffs {
     double alpha[RK_MAX_Q] = {}, beta[RK_MAX_Q] = {};
-    double DM[RK_MAX_Q * RK_MAX_Q] = {}, DK[RK_MAX_Q * RK_MAX_Q] = {};
-    bool dense = false;
+    bool pair = false;      // two inputs: mass-term input, stiffness-term input
+    int premix = 0;         // pair forms: 1 = mass input is (A^-1 (x) I) u, 2 = stiffness input is (A (x) I) u
 };
 
 struct Level {
@@ -113,7 +115,8 @@ struct rk_ctx {
     double* scal = nullptr;        // restart + 16 device scalars
     double* scal2 = nullptr;       // restart + 16
     double* ycoef = nullptr;       // restart
-    double* mix = nullptr;         // 4 x 81: Sinv, S, c1, c2
+    double* mix = nullptr;         // 8 x 81: Sinv, S, rhs coefficients, Ainv S, Ainv, A
+    void* mbuf = nullptr;          // Q N3 (fp64-sized): mixed input of the pair operators
     std::vector<double> host_scal;
     std::vector<Event> events;
     std::vector<Event> event_pool;
@@ -154,8 +157,10 @@ bool valid_options(const rk_options& o, std::string& msg) {
 }
 
 // Coefficients of an operator form on a grid with cell size h:
-//   CALA:   v_s = h^3 sum_j Ainv_sj Mref u_j + tau h Kref u_s      (eq. irk:A)
-//   STAGE:  v_s = h^3 Mref u_s + tau h sum_j A_sj Kref u_j         (stage system)
+//   CALA:   v_s = h^3 Mref (sum_j Ainv_sj u_j) + tau h Kref u_s    (eq. irk:A)
+//   STAGE:  v_s = h^3 Mref u_s + tau h Kref (sum_j A_sj u_j)       (stage system)
+// (the Q x Q mix of the dense forms is applied to the input by a streaming
+// kernel, then the pair operator runs on (mixed input, plain input))
 //   BLOCKS: v_s = lam_s h^3 Mref u_s + tau h Kref u_s              (eq. irk:P blocks)
 //   K, M:   one vector.
 Coeffs make_coeffs(const rk_ctx& c, double h, int form) {
@@ -167,15 +172,11 @@ Coeffs make_coeffs(const rk_ctx& c, double h, int form) {
         if (form == F_K) { r.alpha[s] = 0.0; r.beta[s] = h; }
         if (form == F_M) { r.alpha[s] = h3; r.beta[s] = 0.0; }
     }
-    r.dense = form == F_CALA || form == F_STAGE;
-    for (int s = 0; s < Q; ++s)
-        for (int j = 0; j < Q; ++j) {
-            double dm = 0.0, dk = 0.0;
-            if (form == F_CALA) { dm = h3 * c.tab.Ainv[s * Q + j]; dk = (s == j) ? c.tau * h : 0.0; }
-            if (form == F_STAGE) { dm = (s == j) ? h3 : 0.0; dk = c.tau * h * c.tab.A[s * Q + j]; }
-            r.DM[s * RK_MAX_Q + j] = dm;
-            r.DK[s * RK_MAX_Q + j] = dk;
-        }
+    if (form == F_CALA || form == F_STAGE) {
+        r.pair = true;
+        r.premix = form == F_CALA ? 1 : 2;
+        for (int q = 0; q < Q; ++q) { r.alpha[q] = h3; r.beta[q] = c.tau * h; }
+    }
     return r;
 }
 
@@ -215,7 +216,8 @@ size_t carve(rk_ctx& c, char* base) {
     c.scal = (double*)cv.take(8 * nscal);
     c.scal2 = (double*)cv.take(8 * nscal);
     c.ycoef = (double*)cv.take(8 * (size_t)(m + 16));
-    c.mix = (double*)cv.take(8 * 4 * 81);
+    c.mix = (double*)cv.take(8 * 8 * 81);
+    c.mbuf = cv.take(8 * (size_t)qn);
     return cv.off + kAlign;
 }
 
@@ -274,16 +276,18 @@ struct Timer {
 // ---------------------------------------------------------------------------
 // Operators and the V-cycle.
 // ---------------------------------------------------------------------------
+// One operator launch.  For pair coefficients u is the mass-term input and
+// u2 the stiffness-term input.
 int op(rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, void* v,
-       const void* b, const void* xo, int n, int s0, int ns, int qin, double ca, double cb) {
+       const void* b, const void* xo, int n, int s0, int ns, double ca, double cb,
+       const void* u2 = nullptr) {
     OpLaunch L;
-    L.k = k; L.dtype = dtype; L.mix = cf.dense ? MIX_DENSE : MIX_DIAG; L.epi = epi;
-    L.u = u; L.v = v; L.b = b; L.xo = xo;
+    L.k = k; L.dtype = dtype; L.mix = cf.pair ? MIX_PAIR : MIX_DIAG; L.epi = epi;
+    L.u = u; L.u2 = u2; L.v = v; L.b = b; L.xo = xo;
     for (int i = 0; i < RK_MAX_Q; ++i) { L.alpha[i] = cf.alpha[i]; L.beta[i] = cf.beta[i]; }
-    for (int i = 0; i < RK_MAX_Q * RK_MAX_Q; ++i) { L.DM[i] = cf.DM[i]; L.DK[i] = cf.DK[i]; }
     const long long N = (long long)n * k + 1;
     L.stride = N * N * N;
-    L.n = n; L.s0 = s0; L.nstage = ns; L.qin = qin; L.ca = ca; L.cb = cb;
+    L.n = n; L.s0 = s0; L.nstage = ns; L.ca = ca; L.cb = cb;
     L.stream = c->stream;
     HIPCHK(c, launch_op(L));
     return RK_OK;
@@ -318,7 +322,7 @@ int chebyshev(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, void
         HIPCHK(c, launch_cheb_first(k, dt, to_stage_scal(L.blk), b, first, L.n, s0, ns, 1.0 / cc.theta, c->stream));
         cur = first; prev = nullptr; other = second;
     } else {
-        int rc = op(c, k, dt, EPI_CHEB, L.blk, first, second, b, nullptr, L.n, s0, ns, 1, 0.0, 1.0 / cc.theta);
+        int rc = op(c, k, dt, EPI_CHEB, L.blk, first, second, b, nullptr, L.n, s0, ns, 0.0, 1.0 / cc.theta);
         if (rc) return rc;
         cur = second; prev = first; other = first;
     }
@@ -328,7 +332,7 @@ int chebyshev(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, void
         const double ca = rho_new * rho, cb = 2.0 * rho_new / cc.delta;
         // x_{j+1} overwrites the buffer of x_{j-1} (or the free buffer)
         void* out = prev ? prev : other;
-        int rc = op(c, k, dt, EPI_CHEB, L.blk, cur, out, b, prev, L.n, s0, ns, 1, ca, cb);
+        int rc = op(c, k, dt, EPI_CHEB, L.blk, cur, out, b, prev, L.n, s0, ns, ca, cb);
         if (rc) return rc;
         prev = cur;
         cur = out;
@@ -400,7 +404,7 @@ int vcycle_level(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, v
     if (rc) return rc;
     void* spare = (pre == first) ? second : first;
     // residual into the spare buffer
-    rc = op(c, c->k, c->pc, EPI_RESID, L.blk, pre, spare, b, nullptr, L.n, s0, ns, 1, 0, 0);
+    rc = op(c, c->k, c->pc, EPI_RESID, L.blk, pre, spare, b, nullptr, L.n, s0, ns, 0, 0);
     if (rc) return rc;
     rc = restrict_to(c, l, s0, ns, spare);
     if (rc) return rc;
@@ -435,12 +439,13 @@ int vcycle_all(rk_ctx* c, const void* b, void* x) {
     return RK_OK;
 }
 
-// z = P^-1 r (eq. irk:P); r, z fp64 [Q][N3].
-int precondition(rk_ctx* c, const double* r, double* z) {
+// z = P^-1 r (eq. irk:P); r, z fp64 [Q][N3].  If m is given, m = (A^-1 (x) I) z
+// is written in the same pass (the mass-term input of the operator of eq. irk:A).
+int precondition(rk_ctx* c, const double* r, double* z, double* m = nullptr) {
     Level& F = c->lv[0];
     {
         Timer t(c, C_BASIS);
-        HIPCHK(c, launch_stage_mix(RK_FP64, r, c->pc, F.b, c->mix, c->Q, c->Q, c->N, c->stream));
+        HIPCHK(c, launch_stage_mix(RK_FP64, r, c->pc, F.b, c->mix + kMixSinv, c->Q, c->Q, c->N, c->stream));
     }
     {
         Timer t(c, C_BLOCKS);
@@ -448,7 +453,8 @@ int precondition(rk_ctx* c, const double* r, double* z) {
         if (rc) return rc;
     }
     Timer t(c, C_BASIS);
-    HIPCHK(c, launch_stage_mix(c->pc, F.x, RK_FP64, z, c->mix + 81, c->Q, c->Q, c->N, c->stream));
+    HIPCHK(c, launch_stage_mix(c->pc, F.x, RK_FP64, z, c->mix + kMixS, c->Q, c->Q, c->N, c->stream, m,
+                               m ? c->mix + kMixAinvS : nullptr));
     return RK_OK;
 }
 
@@ -461,7 +467,7 @@ int estimate_eigs(rk_ctx* c) {
         if (L.N <= 2) { L.eig_max = 1.0; continue; }
         HIPCHK(c, launch_random_fill(dt, L.x, L.N, Q, 12345u + 977u * (unsigned)l, c->stream));
         for (int it = 0; it < c->opt.eig_iterations; ++it) {
-            int rc = op(c, c->k, dt, EPI_STORE, L.blk, L.x, L.y, nullptr, nullptr, L.n, 0, Q, 1, 0, 0);
+            int rc = op(c, c->k, dt, EPI_STORE, L.blk, L.x, L.y, nullptr, nullptr, L.n, 0, Q, 0, 0);
             if (rc) return rc;
             HIPCHK(c, launch_power_partial(c->k, dt, to_stage_scal(L.blk), L.x, L.y, L.b, L.n, Q, c->part, kRedBlocks, c->stream));
             HIPCHK(c, launch_reduce(c->part, kRedBlocks, 3 * Q, c->scal, 0, c->stream));
@@ -522,10 +528,11 @@ double device_norm2(rk_ctx* c, const double* x, long long n, int* rc) {
     return v;
 }
 
-int apply_cala(rk_ctx* c, const double* u, double* v, const double* b) {
+// v = (A^-1 (x) M + tau I (x) K) u given m = (A^-1 (x) I) u; with b, v = b - (...) u.
+int apply_cala(rk_ctx* c, const double* u, const double* m, double* v, const double* b) {
     Timer t(c, C_VMULT);
-    return op(c, c->k, RK_FP64, b ? EPI_RESID : EPI_STORE, c->form[F_CALA], u, v, b, nullptr,
-              c->n, 0, c->Q, c->Q, 0, 0);
+    return op(c, c->k, RK_FP64, b ? EPI_RESID : EPI_STORE, c->form[F_CALA], m, v, b, nullptr, c->n, 0,
+              c->Q, 0, 0, u);
 }
 
 }  // namespace
@@ -590,8 +597,19 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
     for (int f = 0; f < F_NFORMS; ++f) c->form[f] = make_coeffs(*c, c->h, f);
     for (auto& L : c->lv) L.blk = make_coeffs(*c, L.h, F_BLOCKS);
     // small Q x Q mixing data: S^-1, S, and the right-hand-side coefficients
-    std::vector<double> mix(4 * 81, 0.0);
-    for (int i = 0; i < Q * Q; ++i) { mix[i] = c->tab.Sinv[i]; mix[81 + i] = c->tab.S[i]; }
+    std::vector<double> mix(8 * 81, 0.0);
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j) {
+            double as = 0.0;
+            for (int l = 0; l < Q; ++l) as += c->tab.Ainv[i * Q + l] * c->tab.S[l * Q + j];
+            mix[kMixAinvS + i * Q + j] = as;
+        }
+    for (int i = 0; i < Q * Q; ++i) {
+        mix[kMixSinv + i] = c->tab.Sinv[i];
+        mix[kMixS + i] = c->tab.S[i];
+        mix[kMixAinv + i] = c->tab.Ainv[i];
+        mix[kMixA + i] = c->tab.A[i];
+    }
     hipError_t e = hipMemcpyAsync(c->mix, mix.data(), mix.size() * 8, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { delete c; return fail(nullptr, RK_EHIP, hipGetErrorString(e)); }
@@ -638,7 +656,14 @@ int rk_apply_operator(rk_ctx* c, int form, int dtype, const void* u, void* v) {
     const size_t bytes = dsize(dtype) * (size_t)ns * c->N3;
     if ((const char*)u < (const char*)v + bytes && (const char*)v < (const char*)u + bytes)
         return fail(c, RK_EINVAL, "u and v overlap");
-    return op(c, c->k, dtype, EPI_STORE, c->form[form], u, v, nullptr, nullptr, c->n, 0, ns, c->Q, 0, 0);
+    const Coeffs& cf = c->form[form];
+    if (!cf.pair) return op(c, c->k, dtype, EPI_STORE, cf, u, v, nullptr, nullptr, c->n, 0, ns, 0, 0);
+    // dense forms: mix the input once, then the pair operator
+    const double* D = c->mix + (cf.premix == 1 ? kMixAinv : kMixA);
+    HIPCHK(c, launch_stage_mix(dtype, u, dtype, c->mbuf, D, c->Q, c->Q, c->N, c->stream));
+    const void* um = cf.premix == 1 ? c->mbuf : u;
+    const void* uk = cf.premix == 1 ? u : c->mbuf;
+    return op(c, c->k, dtype, EPI_STORE, cf, um, v, nullptr, nullptr, c->n, 0, ns, 0, 0, uk);
 }
 
 int rk_vcycle(rk_ctx* c, int dtype, const void* b, void* x) {
@@ -670,7 +695,7 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
     // Right-hand side of eq. (irk:A): rhs_i = sum_j Ainv_ij (gamma_j G - K y).
     {
         Timer t(c, C_RHS);
-        rc = op(c, c->k, RK_FP64, EPI_STORE, c->form[F_K], y, c->Ky, nullptr, nullptr, c->n, 0, 1, 1, 0, 0);
+        rc = op(c, c->k, RK_FP64, EPI_STORE, c->form[F_K], y, c->Ky, nullptr, nullptr, c->n, 0, 1, 0, 0);
         if (rc) return rc;
         double cf[2 * RK_MAX_Q];
         for (int i = 0; i < Q; ++i) {
@@ -681,9 +706,9 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
             }
             cf[i] = c1; cf[RK_MAX_Q + i] = c2;
         }
-        HIPCHK(c, hipMemcpyAsync(c->mix + 162, cf, sizeof(cf), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->mix + kMixRhs, cf, sizeof(cf), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));   // cf lives on the host stack
-        HIPCHK(c, launch_rhs_mix(G, c->Ky, c->rhs, c->mix + 162, c->mix + 162 + RK_MAX_Q, Q, c->N, c->stream));
+        HIPCHK(c, launch_rhs_mix(G, c->Ky, c->rhs, c->mix + kMixRhs, c->mix + kMixRhs + RK_MAX_Q, Q, c->N, c->stream));
     }
     const double bnorm = std::sqrt(device_norm2(c, c->rhs, qn, &rc));
     if (rc) return rc;
@@ -707,10 +732,10 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
         g[0] = rnorm;
         int jd = 0;
         for (int j = 0; j < m && its < c->opt.max_iter; ++j) {
-            rc = precondition(c, c->V + (long long)j * qn, c->Z + (long long)j * qn);
+            rc = precondition(c, c->V + (long long)j * qn, c->Z + (long long)j * qn, (double*)c->mbuf);
             if (rc) return rc;
             vcyc += c->opt.mode == RK_BATCHED ? 1 : Q;
-            rc = apply_cala(c, c->Z + (long long)j * qn, c->w, nullptr);
+            rc = apply_cala(c, c->Z + (long long)j * qn, (const double*)c->mbuf, c->w, nullptr);
             if (rc) return rc;
             {
                 Timer t(c, C_REST);
@@ -752,7 +777,9 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
             HIPCHK(c, hipStreamSynchronize(c->stream));
             HIPCHK(c, launch_combine(c->kv, RK_FP64, c->Z, jd, qn, c->ycoef, qn, c->stream));
         }
-        rc = apply_cala(c, c->kv, c->r, c->rhs);   // true residual r = rhs - A k
+        // true residual r = rhs - A k
+        HIPCHK(c, launch_stage_mix(RK_FP64, c->kv, RK_FP64, c->mbuf, c->mix + kMixAinv, Q, Q, c->N, c->stream));
+        rc = apply_cala(c, c->kv, (const double*)c->mbuf, c->r, c->rhs);
         if (rc) return rc;
     }
     if (!converged) {

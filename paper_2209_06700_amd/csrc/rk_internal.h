@@ -51,7 +51,7 @@ struct StageScal {
 // ---------------------------------------------------------------------------
 // Kernel launchers (implemented in the .hip units).  All return hipError_t.
 // ---------------------------------------------------------------------------
-enum Mix { MIX_DIAG = 0, MIX_DENSE = 1 };
+enum Mix { MIX_DIAG = 0, MIX_PAIR = 1 };
 enum Epi { EPI_STORE = 0, EPI_RESID = 1, EPI_CHEB = 2 };
 
 struct OpLaunch {
@@ -59,18 +59,16 @@ struct OpLaunch {
     int dtype = RK_FP64;
     int mix = MIX_DIAG;
     int epi = EPI_STORE;
-    const void* u = nullptr;   // input vector base (stage 0)
+    const void* u = nullptr;   // input vector base (stage 0); mass-term input for MIX_PAIR
+    const void* u2 = nullptr;  // MIX_PAIR: stiffness-term input base
     void* v = nullptr;         // output vector base (stage 0)
     const void* b = nullptr;   // EPI_RESID / EPI_CHEB right-hand side base
     const void* xo = nullptr;  // EPI_CHEB previous iterate base (nullptr = zero)
-    double alpha[RK_MAX_Q] = {};   // diagonal mix: per-stage scales
-    double beta[RK_MAX_Q] = {};
-    double DM[RK_MAX_Q * RK_MAX_Q] = {};   // dense mix: v_s = M sum_j DM[s][j] u_j
-    double DK[RK_MAX_Q * RK_MAX_Q] = {};   //                + K sum_j DK[s][j] u_j
+    double alpha[RK_MAX_Q] = {};   // per-stage scales: v_s = alpha_s Mref u_s + beta_s Kref u_s
+    double beta[RK_MAX_Q] = {};    // (MIX_PAIR: alpha_s Mref u_s + beta_s Kref u2_s)
     long long stride = 0;      // elements between stages (N^3)
     int n = 0;                 // cells per direction
-    int s0 = 0, nstage = 1;    // output stages [s0, s0 + nstage)
-    int qin = 1;               // dense: number of input stages
+    int s0 = 0, nstage = 1;    // stages [s0, s0 + nstage)
     double ca = 0.0, cb = 0.0; // EPI_CHEB: x_new = x + ca (x - xo) + cb D^-1 (b - A x)
     hipStream_t stream = nullptr;
 };
@@ -99,9 +97,11 @@ hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* 
                              int n, int s0, int nstage, double cb, hipStream_t st);
 
 // out_i = sum_j D[i][j] in_j (D: device doubles, row-major Qout x Qin),
-// computed in double; in/out dtypes independent.  Boundary entries 0.
+// computed in double; in/out dtypes independent.  Boundary entries 0.  If out2
+// is not null, out2_i = sum_j D2[i][j] in_j (fp64) is written in the same pass.
 hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* out,
-                            const double* D, int qout, int qin, int N, hipStream_t st);
+                            const double* D, int qout, int qin, int N, hipStream_t st,
+                            double* out2 = nullptr, const double* D2 = nullptr);
 
 // out_i = c1[i] G + c2[i] w on interior nodes, 0 on boundary nodes (fp64, N
 // nodes per direction); G may be null.  c1, c2: device doubles.
