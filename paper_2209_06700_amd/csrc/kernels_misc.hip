@@ -192,7 +192,9 @@ template <typename Tin, typename Tout>
 __global__ void __launch_bounds__(kBlock) stage_mix_kernel(const Tin* __restrict__ in, Tout* __restrict__ out,
                                                            const double* __restrict__ D, int qout,
                                                            int qin, int N, double* __restrict__ out2,
-                                                           const double* __restrict__ D2) {
+                                                           const double* __restrict__ D2,
+                                                           const double* __restrict__ in_scale) {
+    const double isc = in_scale ? *in_scale : 1.0;
     const int nK = N - 1;
     const long long N3 = (long long)N * N * N;
     for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N3;
@@ -203,7 +205,7 @@ __global__ void __launch_bounds__(kBlock) stage_mix_kernel(const Tin* __restrict
         const bool inner = x > 0 && x < nK && y > 0 && y < nK && z > 0 && z < nK;
         double u[RK_MAX_Q];
 #pragma unroll
-        for (int j = 0; j < RK_MAX_Q; ++j) u[j] = (j < qin && inner) ? (double)in[(long long)j * N3 + r] : 0.0;
+        for (int j = 0; j < RK_MAX_Q; ++j) u[j] = (j < qin && inner) ? isc * (double)in[(long long)j * N3 + r] : 0.0;
 #pragma unroll
         for (int i = 0; i < RK_MAX_Q; ++i) {
             if (i >= qout) break;
@@ -270,21 +272,21 @@ __global__ void __launch_bounds__(kBlock) dots_kernel(const double* __restrict__
     const int nout = nvec + self;
     const long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long step = (long long)gridDim.x * blockDim.x;
-    for (int l0 = 0; l0 < nout; l0 += 8) {
-        double acc[8];
+    for (int l0 = 0; l0 < nout; l0 += 16) {
+        double acc[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+        for (int u = 0; u < 16; ++u) acc[u] = 0.0;
         for (long long i = start; i < n; i += step) {
             const double wi = w[i];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 const int l = l0 + u;
                 if (l < nvec) acc[u] = fma(X[(long long)l * ld + i], wi, acc[u]);
                 else if (l == nvec && self) acc[u] = fma(wi, wi, acc[u]);
             }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 16; ++u) {
             if (l0 + u >= nout) break;
             const double t = block_sum(acc[u], sh);
             if (threadIdx.x == 0) part[(long long)blockIdx.x * nout + l0 + u] = t;
@@ -294,15 +296,24 @@ __global__ void __launch_bounds__(kBlock) dots_kernel(const double* __restrict__
 
 __global__ void __launch_bounds__(kBlock) gs_update_kernel(const double* __restrict__ X, int nvec, long long ld,
                                                            const double* __restrict__ h,
-                                                           double* __restrict__ w, long long n,
+                                                           const double* __restrict__ sig,
+                                                           const double* w, double* out, long long n,
                                                            double* __restrict__ norm_part) {
     __shared__ double sh[kBlock / 64];
+    double coef[16];
     double nrm = 0.0;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         double acc = w[i];
-        for (int l = 0; l < nvec; ++l) acc = fma(-h[l], X[(long long)l * ld + i], acc);
-        w[i] = acc;
+        for (int l0 = 0; l0 < nvec; l0 += 16) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                coef[u] = (l0 + u < nvec) ? h[l0 + u] * (sig ? sig[l0 + u] : 1.0) : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (l0 + u < nvec) acc = fma(-coef[u], X[(long long)(l0 + u) * ld + i], acc);
+        }
+        out[i] = acc;
         nrm = fma(acc, acc, nrm);
     }
     if (norm_part) {
@@ -312,13 +323,18 @@ __global__ void __launch_bounds__(kBlock) gs_update_kernel(const double* __restr
 }
 
 __global__ void reduce_kernel(const double* __restrict__ part, int nblocks, int nout,
-                              double* __restrict__ out, int accumulate) {
+                              double* __restrict__ out, int accumulate, const double* __restrict__ scale,
+                              int nscale, double* __restrict__ inv_sqrt_out) {
     __shared__ double sh[kBlock / 64];
     const int l = blockIdx.x;
     double acc = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += part[(long long)b * nout + l];
-    const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) out[l] = accumulate ? out[l] + t : t;
+    double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        if (scale && l < nscale) t *= scale[l];
+        out[l] = accumulate ? out[l] + t : t;
+        if (inv_sqrt_out && l == nout - 1) *inv_sqrt_out = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) normalize_kernel(double* __restrict__ v, const double* __restrict__ w,
@@ -485,17 +501,18 @@ hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* 
 }
 
 hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* out, const double* D,
-                            int qout, int qin, int N, hipStream_t st, double* out2, const double* D2) {
+                            int qout, int qin, int N, hipStream_t st, double* out2, const double* D2,
+                            const double* in_scale) {
     const long long N3 = (long long)N * N * N;
     dim3 g(grid_for(N3)), b(kBlock);
     if (dtype_in == RK_FP64 && dtype_out == RK_FP64)
-        stage_mix_kernel<double, double><<<g, b, 0, st>>>((const double*)in, (double*)out, D, qout, qin, N, out2, D2);
+        stage_mix_kernel<double, double><<<g, b, 0, st>>>((const double*)in, (double*)out, D, qout, qin, N, out2, D2, in_scale);
     else if (dtype_in == RK_FP64 && dtype_out == RK_FP32)
-        stage_mix_kernel<double, float><<<g, b, 0, st>>>((const double*)in, (float*)out, D, qout, qin, N, out2, D2);
+        stage_mix_kernel<double, float><<<g, b, 0, st>>>((const double*)in, (float*)out, D, qout, qin, N, out2, D2, in_scale);
     else if (dtype_in == RK_FP32 && dtype_out == RK_FP64)
-        stage_mix_kernel<float, double><<<g, b, 0, st>>>((const float*)in, (double*)out, D, qout, qin, N, out2, D2);
+        stage_mix_kernel<float, double><<<g, b, 0, st>>>((const float*)in, (double*)out, D, qout, qin, N, out2, D2, in_scale);
     else
-        stage_mix_kernel<float, float><<<g, b, 0, st>>>((const float*)in, (float*)out, D, qout, qin, N, out2, D2);
+        stage_mix_kernel<float, float><<<g, b, 0, st>>>((const float*)in, (float*)out, D, qout, qin, N, out2, D2, in_scale);
     return hipGetLastError();
 }
 
@@ -512,15 +529,16 @@ hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w,
     return hipGetLastError();
 }
 
-hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, double* w,
-                            long long n, double* norm_part, int nblocks, hipStream_t st) {
-    gs_update_kernel<<<nblocks, kBlock, 0, st>>>(X, nvec, ld, h, w, n, norm_part);
+hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, const double* sig,
+                            const double* w, double* out, long long n, double* norm_part, int nblocks,
+                            hipStream_t st) {
+    gs_update_kernel<<<nblocks, kBlock, 0, st>>>(X, nvec, ld, h, sig, w, out, n, norm_part);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* part, int nblocks, int nout, double* out, int accumulate,
-                         hipStream_t st) {
-    reduce_kernel<<<nout, kBlock, 0, st>>>(part, nblocks, nout, out, accumulate);
+                         hipStream_t st, const double* scale, int nscale, double* inv_sqrt_out) {
+    reduce_kernel<<<nout, kBlock, 0, st>>>(part, nblocks, nout, out, accumulate, scale, nscale, inv_sqrt_out);
     return hipGetLastError();
 }
 

@@ -109,12 +109,12 @@ struct rk_ctx {
     double* w = nullptr;           // Q N3
     double* kv = nullptr;          // Q N3
     double* rhs = nullptr;         // Q N3
-    double* r = nullptr;           // Q N3
     double* Ky = nullptr;          // N3
     double* part = nullptr;        // kRedBlocks x (restart + 8)
     double* scal = nullptr;        // restart + 16 device scalars
     double* scal2 = nullptr;       // restart + 16
     double* ycoef = nullptr;       // restart
+    double* sig = nullptr;         // restart + 2: 1 / ||Vhat_i|| of the Krylov basis
     double* mix = nullptr;         // 8 x 81: Sinv, S, rhs coefficients, Ainv S, Ainv, A
     void* mbuf = nullptr;          // Q N3 (fp64-sized): mixed input of the pair operators
     std::vector<double> host_scal;
@@ -209,13 +209,13 @@ size_t carve(rk_ctx& c, char* base) {
     c.w = (double*)cv.take(8 * qn);
     c.kv = (double*)cv.take(8 * qn);
     c.rhs = (double*)cv.take(8 * qn);
-    c.r = (double*)cv.take(8 * qn);
     c.Ky = (double*)cv.take(8 * c.N3);
     const size_t nscal = std::max(m + 16, 3 * RK_MAX_Q + 1);
     c.part = (double*)cv.take(8 * (size_t)kRedBlocks * nscal);
     c.scal = (double*)cv.take(8 * nscal);
     c.scal2 = (double*)cv.take(8 * nscal);
     c.ycoef = (double*)cv.take(8 * (size_t)(m + 16));
+    c.sig = (double*)cv.take(8 * (size_t)(m + 16));
     c.mix = (double*)cv.take(8 * 8 * 81);
     c.mbuf = cv.take(8 * (size_t)qn);
     return cv.off + kAlign;
@@ -441,11 +441,13 @@ int vcycle_all(rk_ctx* c, const void* b, void* x) {
 
 // z = P^-1 r (eq. irk:P); r, z fp64 [Q][N3].  If m is given, m = (A^-1 (x) I) z
 // is written in the same pass (the mass-term input of the operator of eq. irk:A).
-int precondition(rk_ctx* c, const double* r, double* z, double* m = nullptr) {
+int precondition(rk_ctx* c, const double* r, double* z, double* m = nullptr,
+                 const double* r_scale = nullptr) {
     Level& F = c->lv[0];
     {
         Timer t(c, C_BASIS);
-        HIPCHK(c, launch_stage_mix(RK_FP64, r, c->pc, F.b, c->mix + kMixSinv, c->Q, c->Q, c->N, c->stream));
+        HIPCHK(c, launch_stage_mix(RK_FP64, r, c->pc, F.b, c->mix + kMixSinv, c->Q, c->Q, c->N, c->stream,
+                                   nullptr, nullptr, r_scale));
     }
     {
         Timer t(c, C_BLOCKS);
@@ -485,27 +487,32 @@ int estimate_eigs(rk_ctx* c) {
     return RK_OK;
 }
 
-// Orthogonalise w against V_0..V_j (classical Gram-Schmidt with one
-// conditional re-orthogonalisation) and normalise into V_{j+1}.
-// Returns h[0..j] and h[j+1] = ||w_orth|| on the host.
+// Arnoldi step j.  The basis is stored unnormalised, V_i = sig[i] Vhat_i with
+// the scale factors sig on the device, so no separate normalisation pass is
+// needed.  w = A z_j is orthogonalised against V_0..V_j by classical
+// Gram-Schmidt (one fused dot pass and one update pass); a second pass runs
+// only when the projection cancelled all but 1e-4 of ||w||^2.  The result
+// goes to Vhat_{j+1} and sig[j+1] = 1/||Vhat_{j+1}||.  Returns h[0..j] and
+// h[j+1] = ||w_orth|| on the host.
 int arnoldi_orth(rk_ctx* c, int j, double* hcol) {
     const long long qn = (long long)c->Q * c->N3;
     const int nv = j + 1;
+    double* Vn = c->V + (long long)nv * qn;
     double* hs = c->host_scal.data();
     HIPCHK(c, launch_dots(c->V, nv, qn, c->w, qn, 1, c->part, kRedBlocks, c->stream));
-    HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv + 1, c->scal, 0, c->stream));
-    HIPCHK(c, launch_gs_update(c->V, nv, qn, c->scal, c->w, qn, c->part, kRedBlocks, c->stream));
-    HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream));
+    HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv + 1, c->scal, 0, c->stream, c->sig, nv));
+    HIPCHK(c, launch_gs_update(c->V, nv, qn, c->scal, c->sig, c->w, Vn, qn, c->part, kRedBlocks, c->stream));
+    HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream, nullptr, 0, c->sig + nv));
     HIPCHK(c, hipMemcpyAsync(hs, c->scal, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int i = 0; i < nv; ++i) hcol[i] = hs[i];
-    const double w2 = hs[nv], w2o = hs[nv + 1];
-    double nrm2 = w2o;
-    if (w2o < 0.5 * w2) {
-        HIPCHK(c, launch_dots(c->V, nv, qn, c->w, qn, 0, c->part, kRedBlocks, c->stream));
-        HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv, c->scal2, 0, c->stream));
-        HIPCHK(c, launch_gs_update(c->V, nv, qn, c->scal2, c->w, qn, c->part, kRedBlocks, c->stream));
-        HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream));
+    const double w2 = hs[nv];
+    double nrm2 = hs[nv + 1];
+    if (nrm2 < 1e-4 * w2) {
+        HIPCHK(c, launch_dots(c->V, nv, qn, Vn, qn, 0, c->part, kRedBlocks, c->stream));
+        HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv, c->scal2, 0, c->stream, c->sig, nv));
+        HIPCHK(c, launch_gs_update(c->V, nv, qn, c->scal2, c->sig, Vn, Vn, qn, c->part, kRedBlocks, c->stream));
+        HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream, nullptr, 0, c->sig + nv));
         HIPCHK(c, hipMemcpyAsync(hs, c->scal2, sizeof(double) * nv, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemcpyAsync(hs + nv + 1, c->scal + nv + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -513,14 +520,13 @@ int arnoldi_orth(rk_ctx* c, int j, double* hcol) {
         nrm2 = hs[nv + 1];
     }
     hcol[nv] = std::sqrt(std::max(nrm2, 0.0));
-    if (hcol[nv] > 0)
-        HIPCHK(c, launch_normalize(c->V + (long long)nv * qn, c->w, c->scal + nv + 1, qn, c->stream));
     return RK_OK;
 }
 
-double device_norm2(rk_ctx* c, const double* x, long long n, int* rc) {
+// ||x||^2 on the host; with inv_sqrt, also 1/||x|| into that device scalar.
+double device_norm2(rk_ctx* c, const double* x, long long n, int* rc, double* inv_sqrt = nullptr) {
     hipError_t e = launch_dots(nullptr, 0, 0, x, n, 1, c->part, kRedBlocks, c->stream);
-    if (e == hipSuccess) e = launch_reduce(c->part, kRedBlocks, 1, c->scal, 0, c->stream);
+    if (e == hipSuccess) e = launch_reduce(c->part, kRedBlocks, 1, c->scal, 0, c->stream, nullptr, 0, inv_sqrt);
     double v = 0.0;
     if (e == hipSuccess) e = hipMemcpyAsync(&v, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -713,26 +719,23 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
     const double bnorm = std::sqrt(device_norm2(c, c->rhs, qn, &rc));
     if (rc) return rc;
     HIPCHK(c, launch_fill(RK_FP64, c->kv, qn, 0.0, c->stream));
-    HIPCHK(c, launch_copy(RK_FP64, c->rhs, c->r, qn, c->stream));
+    // the residual of each restart cycle lives in Vhat_0 (k_0 = 0: r = rhs)
+    HIPCHK(c, launch_copy(RK_FP64, c->rhs, c->V, qn, c->stream));
     int its = 0, vcyc = 0;
     double rnorm = bnorm;
     bool converged = bnorm == 0.0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), yv(m);
     while (!converged && its < c->opt.max_iter) {
-        rnorm = std::sqrt(device_norm2(c, c->r, qn, &rc));
+        rnorm = std::sqrt(device_norm2(c, c->V, qn, &rc, c->sig));   // sig[0] = 1/||r||
         if (rc) return rc;
         if (rnorm <= c->opt.rtol * bnorm) { converged = true; break; }
-        {
-            // V_0 = r / ||r||; device_norm2 left ||r||^2 in scal[0]
-            Timer t(c, C_REST);
-            HIPCHK(c, launch_normalize(c->V, c->r, c->scal, qn, c->stream));
-        }
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = rnorm;
         int jd = 0;
         for (int j = 0; j < m && its < c->opt.max_iter; ++j) {
-            rc = precondition(c, c->V + (long long)j * qn, c->Z + (long long)j * qn, (double*)c->mbuf);
+            rc = precondition(c, c->V + (long long)j * qn, c->Z + (long long)j * qn, (double*)c->mbuf,
+                              c->sig + j);
             if (rc) return rc;
             vcyc += c->opt.mode == RK_BATCHED ? 1 : Q;
             rc = apply_cala(c, c->Z + (long long)j * qn, (const double*)c->mbuf, c->w, nullptr);
@@ -779,11 +782,11 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
         }
         // true residual r = rhs - A k
         HIPCHK(c, launch_stage_mix(RK_FP64, c->kv, RK_FP64, c->mbuf, c->mix + kMixAinv, Q, Q, c->N, c->stream));
-        rc = apply_cala(c, c->kv, (const double*)c->mbuf, c->r, c->rhs);
+        rc = apply_cala(c, c->kv, (const double*)c->mbuf, c->V, c->rhs);
         if (rc) return rc;
     }
     if (!converged) {
-        rnorm = std::sqrt(device_norm2(c, c->r, qn, &rc));
+        rnorm = std::sqrt(device_norm2(c, c->V, qn, &rc));
         if (rc) return rc;
         converged = rnorm <= c->opt.rtol * bnorm;
     }

@@ -99,9 +99,11 @@ hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* 
 // out_i = sum_j D[i][j] in_j (D: device doubles, row-major Qout x Qin),
 // computed in double; in/out dtypes independent.  Boundary entries 0.  If out2
 // is not null, out2_i = sum_j D2[i][j] in_j (fp64) is written in the same pass.
+// If in_scale (device scalar) is not null the input is multiplied by it first.
 hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* out,
                             const double* D, int qout, int qin, int N, hipStream_t st,
-                            double* out2 = nullptr, const double* D2 = nullptr);
+                            double* out2 = nullptr, const double* D2 = nullptr,
+                            const double* in_scale = nullptr);
 
 // out_i = c1[i] G + c2[i] w on interior nodes, 0 on boundary nodes (fp64, N
 // nodes per direction); G may be null.  c1, c2: device doubles.
@@ -112,12 +114,16 @@ hipError_t launch_rhs_mix(const double* G, const double* w, double* out, const d
 // l < nvec, and (if self) part[blk * nout + nvec] = sum w[i]^2, nout = nvec + self.
 hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w, long long n,
                        int self, double* part, int nblocks, hipStream_t st);
-// w -= sum_l h[l] X_l; if norm_part: norm_part[blk] = sum (w_new)^2.
-hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, double* w,
-                            long long n, double* norm_part, int nblocks, hipStream_t st);
-// out[l] (+)= sum_b part[b * nout + l] for l < nout (fixed order).
+// out = w - sum_l h[l] sig[l] X_l (sig may be null = ones; out may alias w);
+// if norm_part: norm_part[blk] = sum out^2 over the block's entries.
+hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, const double* sig,
+                            const double* w, double* out, long long n, double* norm_part, int nblocks,
+                            hipStream_t st);
+// out[l] (+)= scale[l] * sum_b part[b * nout + l] for l < nout (fixed order;
+// scale applies to l < nscale).  If inv_sqrt_out: *inv_sqrt_out = 1/sqrt(out[nout-1]).
 hipError_t launch_reduce(const double* part, int nblocks, int nout, double* out, int accumulate,
-                         hipStream_t st);
+                         hipStream_t st, const double* scale = nullptr, int nscale = 0,
+                         double* inv_sqrt_out = nullptr);
 // v = w * (1 / sqrt(*nrm2))
 hipError_t launch_normalize(double* v, const double* w, const double* nrm2, long long n,
                             hipStream_t st);
