@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--op-reps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--cheb-degree", type=int, default=None, help="smoother degree (library default if unset)")
+    ap.add_argument("--cheb-range", type=float, default=None, help="Chebyshev range (library default if unset)")
     ap.add_argument("--mode", choices=["full", "op"], default="full",
                     help="op: only the batched fp32 block operator launches (for counter runs)")
     args = ap.parse_args()
@@ -153,7 +155,12 @@ def main():
         print(json.dumps({"mode": "op", "blocks_fp32_us": t_blk * 1e6, "reps": args.op_reps,
                           "GBps": 8.0 * Q * N ** 3 / t_blk / 1e9}), flush=True)
         return 0
-    solver = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, rtol=1e-10)
+    smoother = {}
+    if args.cheb_degree is not None:
+        smoother.update(cheb_degree=args.cheb_degree, coarse_cheb_degree=args.cheb_degree)
+    if args.cheb_range is not None:
+        smoother["cheb_range"] = args.cheb_range
+    solver = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, rtol=1e-10, **smoother)
     ctx = solver.ctx
     # operator throughput: batched fp32 block operator, all Q stages per launch
     u32 = torch.randn(Q * N ** 3, dtype=torch.float32, device="cuda")
@@ -188,7 +195,8 @@ def main():
     log(f"[bench] {t_step * 1e3:.2f} ms/step, FGMRES its {its}")
     # per-component breakdown of one extra step
     solver.close()
-    solver = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, rtol=1e-10, timing=1)
+    solver = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, rtol=1e-10, timing=1,
+                        **smoother)
     breakdown = solver.step(t, y)
     solver.close()
     del y
@@ -210,7 +218,8 @@ def main():
         "config": {"workload": f"{n}^3 hex cells, Q_4 ({N}^3 nodes/stage), Radau IIA Q={Q}, tau={tau}, "
                                f"mixed precision, batched stages",
                    "n_cells": n, "degree": k, "Q": Q, "tau": tau, "stage_dofs": sdofs,
-                   "precision": "mixed", "mode": "batched", "rtol": 1e-10, "cheb_degree": 3},
+                   "precision": "mixed", "mode": "batched", "rtol": 1e-10,
+                   "cheb_degree": solver.opts.cheb_degree, "cheb_range": solver.opts.cheb_range},
         "s_per_step": t_step,
         "fgmres_iterations_per_step": its,
         "vcycles_per_step": vcs,

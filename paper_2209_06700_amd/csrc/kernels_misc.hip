@@ -151,10 +151,9 @@ hipError_t transfer_k(const TransferLaunch& L) {
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi diagonal of the diagonal-mix record operator at node (x, y, z).
-// ---------------------------------------------------------------------------
 // Jacobi diagonal of the diagonal-mix operator (scales alpha, beta) at node
 // (x, y, z) of a degree-k grid.
+// ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T jacobi_diag(int k, T alpha, T beta, int x, int y, int z) {
     const T mx = T(kTab.dM[k][x % k]), my = T(kTab.dM[k][y % k]), mz = T(kTab.dM[k][z % k]);
@@ -162,26 +161,47 @@ __device__ __forceinline__ T jacobi_diag(int k, T alpha, T beta, int x, int y, i
     return fma(alpha, mx * my * mz, beta * (kx * my * mz + mx * ky * mz + mx * my * kz));
 }
 
+// 1/d; fp32 takes the hardware reciprocal (the smoother is a preconditioner)
+template <typename T>
+__device__ __forceinline__ T smoother_recip(T d) {
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(d);
+    else return T(1) / d;
+}
+
+// First Chebyshev iterate from a zero guess: x = cb D^-1 b on interior nodes,
+// 0 on the boundary.  Block (64, 4) covers four node rows; grid (ceil(N / 4),
+// N * nstage) gives every block one (stage, z) plane slice, so no thread
+// divides a flat index.
+constexpr int kRowThreads = 64, kRows = kBlock / kRowThreads;
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) cheb_first_kernel(Scal<T> sc, int k,
                                                             const T* __restrict__ b, T* __restrict__ x,
-                                                            int n, int s0, int nstage, T cb) {
+                                                            int n, int s0, T cb) {
     const int nK = n * k, N = nK + 1;
-    const long long N3 = (long long)N * N * N;
-    const long long total = N3 * nstage;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const int sl = (int)(idx / N3);
-        const long long r = idx - (long long)sl * N3;
-        const int z = (int)(r / ((long long)N * N));
-        const int rr = (int)(r - (long long)z * N * N);
-        const int y = rr / N, xx = rr - y * N;
-        const int s = s0 + sl;
-        const long long off = (long long)s * N3 + r;
+    const int y = blockIdx.x * kRows + threadIdx.y;
+    const int sl = blockIdx.y / N, z = blockIdx.y - sl * N;
+    if (y >= N) return;
+    const int s = s0 + sl;
+    const long long row = (long long)s * N * N * N + ((long long)z * N + y) * N;
+    const bool yz_in = y > 0 && y < nK && z > 0 && z < nK;
+    const int ry = y % k, rz = z % k;
+    const T my = T(kTab.dM[k][ry]), mz = T(kTab.dM[k][rz]);
+    const T ky = T(kTab.dA[k][ry]), kz = T(kTab.dA[k][rz]);
+    const T myz = my * mz, kyz = ky * mz + my * kz;
+    const T al = sc.alpha[s], be = sc.beta[s];
+    const int step = kRowThreads % k;
+    int r = threadIdx.x % k;
+    for (int xx = threadIdx.x; xx < N; xx += kRowThreads) {
         T val = T(0);
-        if (xx > 0 && xx < nK && y > 0 && y < nK && z > 0 && z < nK)
-            val = cb * b[off] / jacobi_diag(k, sc.alpha[s], sc.beta[s], xx, y, z);
-        x[off] = val;
+        if (yz_in && xx > 0 && xx < nK) {
+            const T mx = T(kTab.dM[k][r]), kx = T(kTab.dA[k][r]);
+            const T D = fma(al, mx * myz, be * fma(kx, myz, mx * kyz));
+            val = cb * b[row + xx] * smoother_recip(D);
+        }
+        x[row + xx] = val;
+        r += step;
+        if (r >= k) r -= k;
     }
 }
 
@@ -300,21 +320,25 @@ __global__ void __launch_bounds__(kBlock) gs_update_kernel(const double* __restr
                                                            const double* w, double* out, long long n,
                                                            double* __restrict__ norm_part) {
     __shared__ double sh[kBlock / 64];
-    double coef[16];
     double nrm = 0.0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        double acc = w[i];
-        for (int l0 = 0; l0 < nvec; l0 += 16) {
+    const long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long step = (long long)gridDim.x * blockDim.x;
+    // 16 basis vectors per sweep; a single sweep for the usual basis sizes
+    for (int l0 = 0; l0 < nvec || l0 == 0; l0 += 16) {
+        double coef[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-                coef[u] = (l0 + u < nvec) ? h[l0 + u] * (sig ? sig[l0 + u] : 1.0) : 0.0;
+        for (int u = 0; u < 16; ++u)
+            coef[u] = (l0 + u < nvec) ? h[l0 + u] * (sig ? sig[l0 + u] : 1.0) : 0.0;
+        const bool last = l0 + 16 >= nvec;
+        const double* src = l0 == 0 ? w : out;
+        for (long long i = start; i < n; i += step) {
+            double acc = src[i];
 #pragma unroll
             for (int u = 0; u < 16; ++u)
                 if (l0 + u < nvec) acc = fma(-coef[u], X[(long long)(l0 + u) * ld + i], acc);
+            out[i] = acc;
+            if (last) nrm = fma(acc, acc, nrm);
         }
-        out[i] = acc;
-        nrm = fma(acc, acc, nrm);
     }
     if (norm_part) {
         const double t = block_sum(nrm, sh);
@@ -491,12 +515,12 @@ hipError_t launch_transfer(const TransferLaunch& L) {
 
 hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* b, void* x, int n,
                              int s0, int nstage, double cb, hipStream_t st) {
-    const long long N = (long long)n * k + 1;
-    dim3 g(grid_for(N * N * N * nstage)), blk(kBlock);
+    const int N = n * k + 1;
+    dim3 g((N + kRows - 1) / kRows, N * nstage), blk(kRowThreads, kRows);
     if (dtype == RK_FP64)
-        cheb_first_kernel<double><<<g, blk, 0, st>>>(to_scal<double>(sc), k, (const double*)b, (double*)x, n, s0, nstage, cb);
+        cheb_first_kernel<double><<<g, blk, 0, st>>>(to_scal<double>(sc), k, (const double*)b, (double*)x, n, s0, cb);
     else
-        cheb_first_kernel<float><<<g, blk, 0, st>>>(to_scal<float>(sc), k, (const float*)b, (float*)x, n, s0, nstage, (float)cb);
+        cheb_first_kernel<float><<<g, blk, 0, st>>>(to_scal<float>(sc), k, (const float*)b, (float*)x, n, s0, (float)cb);
     return hipGetLastError();
 }
 

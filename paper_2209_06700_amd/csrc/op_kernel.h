@@ -352,35 +352,53 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
     const T* __restrict__ bs = (EPI != EPI_STORE) ? p.b + (long long)s * p.stride : nullptr;
     const T* xos = (EPI == EPI_CHEB && !p.xo_zero) ? p.xo + (long long)s * p.stride : nullptr;
 
-    // value written at an interior node (c, a) of the completed element
-    auto epi_value = [&](auto cm, auto am, long long gofs) __attribute__((always_inline)) {
+    // 1 / D for the Chebyshev epilogue (fp32: hardware reciprocal; the
+    // smoother is a preconditioner, so the last-bit rounding is immaterial)
+    auto recip = [](T d) __attribute__((always_inline)) {
+        if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(d);
+        else return T(1) / d;
+    };
+    // Jacobi diagonal of the block operator at node (c, a) of the pencil
+    auto jac = [&](auto cm, auto am) __attribute__((always_inline)) {
         constexpr int c = decltype(cm)::value;
         constexpr int a = decltype(am)::value;
-        const T av = acc[c][a];
-        if (EPI == EPI_STORE) return av;
-        if (EPI == EPI_RESID) return bs[gofs] - av;
         constexpr T dmy = T(DG<K, 0, a>::v), dky = T(DG<K, 1, a>::v);
         constexpr T dmz = T(DG<K, 0, c>::v), dkz = T(DG<K, 1, c>::v);
         const T dM = dmx * (dmy * dmz);
         const T dK = dkx * (dmy * dmz) + dmx * (dky * dmz + dmy * dkz);
-        const T D = fma(alpha, dM, beta * dK);
-        const T x = us[gofs];
-        const T xo = xos ? xos[gofs] : T(0);
-        return x + p.ca * (x - xo) + p.cb * (bs[gofs] - av) / D;
+        return fma(alpha, dM, beta * dK);
     };
 
     // Pencils whose nodes are all interior in x and y take the branch-free path.
     const bool pencil_inner = colok && !xbnd && gy0 > 0 && gy0 + K - 1 < nK;
-    // Write the K completed output planes of element e.
+    // Write the K completed output planes of element e.  Per output plane the
+    // epilogue loads of its K nodes are issued together before any use.
     auto flush = [&](int e) __attribute__((always_inline)) {
         if (pencil_inner && e > 0) {
             cfor<K>([&](auto cm) {
                 constexpr int c = decltype(cm)::value;
                 const long long zo = (long long)(e * K + c) * NN;
+                T lb[K], lx[K], lo[K];
+                if (EPI != EPI_STORE) {
+                    cfor<K>([&](auto am) {
+                        constexpr int a = decltype(am)::value;
+                        const long long ro = zo + (long long)a * N;
+                        lb[a] = (bs + ro)[colbase];
+                        if (EPI == EPI_CHEB) {
+                            lx[a] = (us + ro)[colbase];
+                            lo[a] = xos ? (xos + ro)[colbase] : T(0);
+                        }
+                    });
+                }
                 cfor<K>([&](auto am) {
                     constexpr int a = decltype(am)::value;
                     const long long ro = zo + (long long)a * N;     // uniform row offset
-                    (vs + ro)[colbase] = epi_value(cm, am, ro + colbase);
+                    const T av = acc[c][a];
+                    T out;
+                    if (EPI == EPI_STORE) out = av;
+                    else if (EPI == EPI_RESID) out = lb[a] - av;
+                    else out = lx[a] + p.ca * (lx[a] - lo[a]) + p.cb * (lb[a] - av) * recip(jac(cm, am));
+                    (vs + ro)[colbase] = out;
                 });
             });
             return;
@@ -396,7 +414,19 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
                 if (y < N) {
                     const unsigned off = colbase + (unsigned)(a * N);
                     const bool bnd = z == 0 || xbnd || y == 0 || y == nK;
-                    (vs + zo)[off] = bnd ? T(0) : epi_value(cm, am, zo + off);
+                    T out = T(0);
+                    if (!bnd) {
+                        const T av = acc[c][a];
+                        const long long g = zo + off;
+                        if (EPI == EPI_STORE) out = av;
+                        else if (EPI == EPI_RESID) out = bs[g] - av;
+                        else {
+                            const T x = us[g];
+                            const T xo = xos ? xos[g] : T(0);
+                            out = x + p.ca * (x - xo) + p.cb * (bs[g] - av) * recip(jac(cm, am));
+                        }
+                    }
+                    (vs + zo)[off] = out;
                 }
             });
         });
@@ -508,7 +538,7 @@ hipError_t launch_op_typed(const OpLaunch& L) {
     // z-chunk length: long enough to amortise the k re-read planes, short
     // enough to give every CU several workgroups
     int cz = 16;
-    while (cz > 2 && (long long)p.tiles_x * p.tiles_y * ((L.n + cz - 1) / cz) * L.nstage < 2048) cz /= 2;
+    while (cz > 1 && (long long)p.tiles_x * p.tiles_y * ((L.n + cz - 1) / cz) * L.nstage < 2048) cz /= 2;
     if (const char* env = std::getenv("RK_OP_CZ")) cz = std::max(1, std::atoi(env));   // tuning override
     p.cz = cz;
     p.chunks_z = (N + cz * K - 1) / (cz * K);

@@ -42,7 +42,7 @@ hipError_t launch_op(const OpLaunch& L) {
 
 namespace {
 
-constexpr int kRedBlocks = 1024;     // blocks of the reduction kernels
+constexpr int kRedBlocks = 2048;     // blocks of the reduction kernels
 // slots (x 81 doubles) of the device Q x Q mixing data
 constexpr int kMixSinv = 0, kMixS = 81, kMixRhs = 162, kMixAinvS = 243, kMixAinv = 324, kMixA = 405;
 constexpr size_t kAlign = 256;
@@ -224,6 +224,9 @@ size_t carve(rk_ctx& c, char* base) {
 int setup_sizes(rk_ctx& c, const rk_mesh* mesh, int degree, int Q, const rk_options* opt) {
     if (!mesh || mesh->n_cells < 1 || degree < 1 || degree > RK_MAX_DEGREE || Q < 1 || Q > RK_MAX_Q)
         return fail(nullptr, RK_EINVAL, "mesh, degree (1..6) or Q (1..9) out of range");
+    // launch grids put (stage, z-plane) pairs in one grid dimension (<= 65535)
+    if ((long long)mesh->n_cells * degree + 1 > 65535 / Q)
+        return fail(nullptr, RK_EINVAL, "grid too large: (n_cells * degree + 1) * Q must not exceed 65535");
     if (opt) c.opt = *opt;
     else rk_default_options(&c.opt);
     std::string msg;
