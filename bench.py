@@ -13,12 +13,18 @@ Reported:
   as in the paper's DoF table), timed with HIP events on the library stream;
 * ms_per_step: wall time of one Radau IIA step (K steps timed after W
   warm-up steps, synchronised on both sides);
-* roofline of that operator kernel (HBM bound; algorithmic bytes = read u +
-  write v = 8 B per stage-DoF in fp32);
+* roofline of that operator kernel: it is bound by fp32 vector arithmetic
+  (84 flop per stage-DoF for Q_4 against the 78.6 TFLOP/s non-packed fp32
+  rate), with the HBM view (8 B per stage-DoF against 8 TB/s) beside it and
+  the HBM bytes that the FETCH_SIZE / WRITE_SIZE counters measured;
 * cpu_baseline: the oracle's assembled block operator (scipy CSR SpMV) on a
   bounded sample (16^3 cells, Q_4, same Q and tau), in the same unit.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+       python bench.py --mode op [--op-reps R]      (operator launches + one
+           device copy of the same size, for counter runs)
+       python bench.py --traffic-from FETCH.csv WRITE.csv   (turn two
+           rocprofv3 --pmc runs of --mode op into the committed traffic record)
 """
 from __future__ import annotations
 
@@ -34,6 +40,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "stage-DoFs/s of batched matrix-free operator; s per Radau step at 1e-8 tol"
 HBM_PEAK_GBS = 8000.0
+# fp32 vector rate without packed instructions: 256 CUs x 4 SIMDs x 16 lanes
+# x 2 flop (FMA) x 2.4 GHz
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+OP_KERNEL = "op_kernel<4, float, MIX_DIAG, EPI_STORE>"
+OP_KERNEL_MANGLED = "_ZN2rk3dev9op_kernelILi4EfLi0ELi0EEEvNS0_6OpArgsIT0_EE"
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def op_flops_per_stage_dof(k: int) -> float:
+    """Arithmetic of the sum-factorised block operator per output node and
+    stage (multiply-add = 2 flop): x-pass 2 banded 1D products (2k+3 flop per
+    node each) + 4 flop of scaling, y-pass 3 products + 1 add, z-pass
+    4(k+1) flop per plane plus the element-start terms (3(k+1)+1)/k."""
+    return (2 * (2 * k + 3) + 4) + (3 * (2 * k + 3) + 1) + 4 * (k + 1) + (3 * (k + 1) + 1) / k
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_op_blocks_fp32_64cubed_q4.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2209_06700_amd", "csrc", "op_kernel.h")
 
@@ -60,8 +80,53 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
+def _counter_rows(path, counter):
+    """(kernel name, value) of every dispatch in a rocprofv3 counter_collection.csv."""
+    import csv
+    out = []
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            if row["Counter_Name"] == counter:
+                out.append((row["Kernel_Name"], float(row["Counter_Value"])))
+    return out
+
+
+def traffic_record(fetch_csv, write_csv, n=64, k=4, Q=4):
+    """HBM bytes per launch of the operator kernel: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch, one rocprofv3 --pmc run each), each scaled by the ratio
+    of the known size of a plain device copy to what the same counter read for
+    that copy in the same run."""
+    N = n * k + 1
+    copy_bytes = 4.0 * Q * N ** 3
+    rec = {"kernel": OP_KERNEL, "workload": f"{n}^3 cells Q_{k}, Q={Q}, fp32 block operator",
+           "kernel_source_sha256_16": kernel_hash(), "copy_kernel": COPY_KERNEL, "copy_bytes": copy_bytes,
+           "algorithmic_bytes_per_launch": 8.0 * Q * N ** 3,
+           "commands": [f"rocprofv3 --pmc {c} -d gpurun_out/pmc_{c.split('_')[0].lower()} -o op "
+                        f"--output-format csv -- python bench.py --mode op --op-reps 3"
+                        for c in ("FETCH_SIZE", "WRITE_SIZE")]
+                       + ["python bench.py --traffic-from gpurun_out/pmc_fetch/op_counter_collection.csv "
+                          "gpurun_out/pmc_write/op_counter_collection.csv"]}
+    total = 0.0
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _counter_rows(path, counter)
+        op = [v for nm, v in rows if nm.startswith(OP_KERNEL_MANGLED) or "op_kernel<4, float, 0, 0>" in nm]
+        cp = [v for nm, v in rows if COPY_KERNEL in nm]
+        if not op or not cp:
+            raise SystemExit(f"{path}: no {counter} rows for the operator or the copy kernel")
+        kib_op = sum(op) / len(op)
+        kib_cp = cp[-1]
+        scale = copy_bytes / (kib_cp * 1024.0)
+        rec[counter] = {"op_kib_per_dispatch": kib_op, "op_dispatches": len(op), "copy_kib": kib_cp,
+                        "scale": scale, "op_bytes_per_launch": kib_op * 1024.0 * scale}
+        total += kib_op * 1024.0 * scale
+    rec["hbm_bytes_per_launch"] = total
+    rec["bytes_per_stage_dof"] = total / (Q * N ** 3)
+    return rec
+
+
 def time_op(torch, R, ctx, form, u, v, reps):
-    stream = torch.cuda.current_stream()
+    """Average launch time of rk_apply_operator, HIP events on the context's stream."""
+    stream = ctx.stream
     R.rk_apply_operator(ctx, form, u, v)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -133,7 +198,15 @@ def main():
     ap.add_argument("--cheb-range", type=float, default=None, help="Chebyshev range (library default if unset)")
     ap.add_argument("--mode", choices=["full", "op"], default="full",
                     help="op: only the batched fp32 block operator launches (for counter runs)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic record from two rocprofv3 --pmc runs of --mode op")
     args = ap.parse_args()
+    if args.traffic_from:
+        rec = traffic_record(*args.traffic_from, n=args.n)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU decomposition is a design note only)", file=sys.stderr)
@@ -152,8 +225,14 @@ def main():
         u32 = torch.randn(Q * N ** 3, dtype=torch.float32, device="cuda")
         v32 = torch.empty_like(u32)
         t_blk = time_op(torch, R, solver.ctx, R.RK_OP_BLOCKS, u32, v32, args.op_reps)
-        print(json.dumps({"mode": "op", "blocks_fp32_us": t_blk * 1e6, "reps": args.op_reps,
-                          "GBps": 8.0 * Q * N ** 3 / t_blk / 1e9}), flush=True)
+        # one plain device-to-device copy of the same size: the reference
+        # dispatch that scales the byte counters
+        with torch.cuda.stream(solver.ctx.stream):
+            v32.copy_(u32)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "op", "kernel": OP_KERNEL, "blocks_fp32_us": t_blk * 1e6,
+                          "reps": args.op_reps, "GBps": 8.0 * Q * N ** 3 / t_blk / 1e9,
+                          "copy_bytes": u32.numel() * 4}), flush=True)
         return 0
     smoother = {}
     if args.cheb_degree is not None:
@@ -201,7 +280,9 @@ def main():
     solver.close()
     del y
     torch.cuda.empty_cache()
-    achieved = 8.0 * sdofs / t_blk / 1e9
+    flop = op_flops_per_stage_dof(k)
+    achieved = flop * sdofs / t_blk / 1e12
+    hbm_gbs = 8.0 * sdofs / t_blk / 1e9
     out = {
         "metric": METRIC,
         "value": sdofs / t_blk,
@@ -231,10 +312,13 @@ def main():
             "cala_fp64_stage_dofs_per_s": sdofs / t_cala,
             "cala_fp64_GBps": 16.0 * sdofs / t_cala / 1e9,
         },
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "op_kernel<4,float,diag,store> (batched block operator)",
-                     "algorithmic_bytes_per_launch": 8 * sdofs},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "kernel": OP_KERNEL + " (batched block operator, all Q stages per launch)",
+                     "flop_per_stage_dof": flop, "algorithmic_flop_per_launch": flop * sdofs,
+                     "avg_launch_us": t_blk * 1e6,
+                     "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": hbm_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": 8 * sdofs}},
     }
     if not args.no_cpu:
         log("[bench] accuracy vs oracle on 32^3 and cpu baseline")
