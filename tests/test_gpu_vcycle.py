@@ -139,3 +139,21 @@ def test_eigen_estimate_is_safe(R, n, k, Q, tau):
             continue
         exact = mg.max_eig_exact(l)
         assert 0.9 * 1.2 * exact <= est[l] <= 1.2 * exact * (1 + 1e-9), (l, est[l], exact)
+
+
+@pytest.mark.parametrize("Q", list(range(1, 10)))
+def test_setup_tableau_matches_oracle(R, Q):
+    """The library's extended-precision tableau, Crout factor and real
+    eigen-decomposition (rk_info) against the oracle's 50-digit ones."""
+    from oracle.tableau import RadauIIA
+    tab = RadauIIA(Q)
+    s = R.RadauIIA(2, 1, Q, 0.1)
+    info = s.info
+    s.close()
+    for key, want in (("A", tab.A), ("b", tab.b), ("c", tab.c), ("Ainv", tab.Ainv), ("L", tab.L),
+                      ("S", tab.S), ("Sinv", tab.Sinv), ("lam", tab.lam)):
+        got = np.asarray(info[key]).reshape(np.shape(want))
+        scale = max(1.0, float(np.abs(want).max()))
+        # S is ill-conditioned for large Q; entries agree to ~cond(S) eps
+        tol = 1e-13 if key not in ("S", "Sinv") else 1e-13 * np.linalg.cond(tab.S)
+        assert np.abs(got - want).max() <= tol * scale, (key, np.abs(got - want).max())
