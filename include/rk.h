@@ -83,7 +83,7 @@ extern "C" {
 typedef struct rk_ctx rk_ctx;
 
 /* Uniform mesh of [0,1]^3 with n_cells^3 hexahedra (n_cells = 2^L in Sec. 5;
-   any n_cells >= 1 here, with (n_cells*degree + 1) * Q <= 65535).  Multigrid
+   any n_cells >= 1 here, with N = n_cells*degree + 1 <= 16384 and N*Q <= 65535).  Multigrid
    levels halve n_cells while it is even. */
 typedef struct {
     int32_t n_cells;

@@ -4,6 +4,10 @@
 // coalesced x-fastest access.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdint>
+#include <utility>
+
 #include "element_data.h"
 #include "rk_internal.h"
 
@@ -284,60 +288,134 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;   // valid in thread 0
 }
 
-// dots of w against X_l, 8 vectors per sweep over w
-__global__ void __launch_bounds__(kBlock) dots_kernel(const double* __restrict__ X, int nvec, long long ld,
-                                                      const double* __restrict__ w, long long n,
-                                                      int self, double* __restrict__ part) {
+// ---------------------------------------------------------------------------
+// Krylov vector kernels.  Each launch handles a chunk of NV <= 16 basis
+// vectors (compile time, so every load of an iteration is issued before the
+// arithmetic that uses it); with V2 every thread moves two consecutive
+// entries per vector (16-byte loads; needs 16-byte aligned vectors and an even
+// leading dimension).  Sums run over a fixed grid with a fixed per-thread
+// order, so results are reproducible run to run.
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 16;
+
+template <typename F, int... I>
+hipError_t dispatch_nv_impl(int nv, F&& f, std::integer_sequence<int, I...>) {
+    hipError_t e = hipErrorInvalidValue;
+    ((nv == I + 1 ? (e = f(std::integral_constant<int, I + 1>{}), 0) : 0), ...);
+    return e;
+}
+// f(integral_constant<int, nv>) for nv in 1..kChunk
+template <typename F>
+hipError_t dispatch_nv(int nv, F&& f) {
+    return dispatch_nv_impl(nv, f, std::make_integer_sequence<int, kChunk>{});
+}
+
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> { using type = double2; };
+template <>
+struct Pair<float> { using type = float2; };
+
+// part[blk * nout + l0 + u] = sum over the block's entries of X_u[i] w[i]
+// (u < NV), and if self: part[blk * nout + l0 + NV] = sum w[i]^2.
+template <int NV, bool V2>
+__global__ void __launch_bounds__(kBlock) dots_kernel(const double* __restrict__ X, long long ld,
+                                                      const double* __restrict__ w, long long n, int self,
+                                                      double* __restrict__ part, int nout, int l0) {
     __shared__ double sh[kBlock / 64];
-    const int nout = nvec + self;
-    const long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int NA = NV > 0 ? NV : 1;
+    double acc[NA], accs = 0.0;
+#pragma unroll
+    for (int u = 0; u < NA; ++u) acc[u] = 0.0;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long step = (long long)gridDim.x * blockDim.x;
-    for (int l0 = 0; l0 < nout; l0 += 16) {
-        double acc[16];
+    if constexpr (V2) {
+        const long long n2 = n >> 1;
+        for (long long i = tid; i < n2; i += step) {
+            const double2 wi = reinterpret_cast<const double2*>(w)[i];
+            double2 xv[NA];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-        for (long long i = start; i < n; i += step) {
+            for (int u = 0; u < NV; ++u) xv[u] = reinterpret_cast<const double2*>(X + u * ld)[i];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) acc[u] = fma(xv[u].y, wi.y, fma(xv[u].x, wi.x, acc[u]));
+            accs = fma(wi.y, wi.y, fma(wi.x, wi.x, accs));
+        }
+        if ((n & 1) && tid == 0) {
+            const double wi = w[n - 1];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) acc[u] = fma(X[u * ld + n - 1], wi, acc[u]);
+            accs = fma(wi, wi, accs);
+        }
+    } else {
+        for (long long i = tid; i < n; i += step) {
             const double wi = w[i];
+            double xv[NA];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int l = l0 + u;
-                if (l < nvec) acc[u] = fma(X[(long long)l * ld + i], wi, acc[u]);
-                else if (l == nvec && self) acc[u] = fma(wi, wi, acc[u]);
-            }
-        }
+            for (int u = 0; u < NV; ++u) xv[u] = X[u * ld + i];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            if (l0 + u >= nout) break;
-            const double t = block_sum(acc[u], sh);
-            if (threadIdx.x == 0) part[(long long)blockIdx.x * nout + l0 + u] = t;
+            for (int u = 0; u < NV; ++u) acc[u] = fma(xv[u], wi, acc[u]);
+            accs = fma(wi, wi, accs);
         }
+    }
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const double t = block_sum(acc[u], sh);
+        if (threadIdx.x == 0) part[(long long)blockIdx.x * nout + l0 + u] = t;
+    }
+    if (self) {
+        const double t = block_sum(accs, sh);
+        if (threadIdx.x == 0) part[(long long)blockIdx.x * nout + l0 + NV] = t;
     }
 }
 
-__global__ void __launch_bounds__(kBlock) gs_update_kernel(const double* __restrict__ X, int nvec, long long ld,
+// out = src - sum_u h[u] sig[u] X_u (sig may be null; out may alias src);
+// if norm_part: norm_part[blk] = sum of out^2 over the block's entries.
+template <int NV, bool V2>
+__global__ void __launch_bounds__(kBlock) gs_update_kernel(const double* __restrict__ X, long long ld,
                                                            const double* __restrict__ h,
                                                            const double* __restrict__ sig,
-                                                           const double* w, double* out, long long n,
+                                                           const double* src, double* out, long long n,
                                                            double* __restrict__ norm_part) {
     __shared__ double sh[kBlock / 64];
+    double coef[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) coef[u] = -h[u] * (sig ? sig[u] : 1.0);
     double nrm = 0.0;
-    const long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long step = (long long)gridDim.x * blockDim.x;
-    // 16 basis vectors per sweep; a single sweep for the usual basis sizes
-    for (int l0 = 0; l0 < nvec || l0 == 0; l0 += 16) {
-        double coef[16];
+    if constexpr (V2) {
+        const long long n2 = n >> 1;
+        for (long long i = tid; i < n2; i += step) {
+            double2 acc = reinterpret_cast<const double2*>(src)[i];
+            double2 xv[NV];
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-            coef[u] = (l0 + u < nvec) ? h[l0 + u] * (sig ? sig[l0 + u] : 1.0) : 0.0;
-        const bool last = l0 + 16 >= nvec;
-        const double* src = l0 == 0 ? w : out;
-        for (long long i = start; i < n; i += step) {
+            for (int u = 0; u < NV; ++u) xv[u] = reinterpret_cast<const double2*>(X + u * ld)[i];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) {
+                acc.x = fma(coef[u], xv[u].x, acc.x);
+                acc.y = fma(coef[u], xv[u].y, acc.y);
+            }
+            reinterpret_cast<double2*>(out)[i] = acc;
+            nrm = fma(acc.y, acc.y, fma(acc.x, acc.x, nrm));
+        }
+        if ((n & 1) && tid == 0) {
+            double acc = src[n - 1];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) acc = fma(coef[u], X[u * ld + n - 1], acc);
+            out[n - 1] = acc;
+            nrm = fma(acc, acc, nrm);
+        }
+    } else {
+        for (long long i = tid; i < n; i += step) {
             double acc = src[i];
+            double xv[NV];
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-                if (l0 + u < nvec) acc = fma(-coef[u], X[(long long)(l0 + u) * ld + i], acc);
+            for (int u = 0; u < NV; ++u) xv[u] = X[u * ld + i];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) acc = fma(coef[u], xv[u], acc);
             out[i] = acc;
-            if (last) nrm = fma(acc, acc, nrm);
+            nrm = fma(acc, acc, nrm);
         }
     }
     if (norm_part) {
@@ -369,15 +447,44 @@ __global__ void __launch_bounds__(kBlock) normalize_kernel(double* __restrict__ 
         v[i] = w[i] * inv;
 }
 
-template <typename TZ>
-__global__ void __launch_bounds__(kBlock) combine_kernel(double* __restrict__ kv, const TZ* __restrict__ Z, int nz,
+// kv += sum_u y[u] Z_u for a chunk of NV vectors (Z fp64 or fp32)
+template <int NV, typename TZ, bool V2>
+__global__ void __launch_bounds__(kBlock) combine_kernel(double* __restrict__ kv, const TZ* __restrict__ Z,
                                                          long long ld, const double* __restrict__ y,
                                                          long long n) {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        double acc = kv[i];
-        for (int j = 0; j < nz; ++j) acc = fma(y[j], (double)Z[(long long)j * ld + i], acc);
-        kv[i] = acc;
+    double coef[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) coef[u] = y[u];
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long step = (long long)gridDim.x * blockDim.x;
+    if constexpr (V2) {
+        using P2 = typename Pair<TZ>::type;
+        const long long n2 = n >> 1;
+        for (long long i = tid; i < n2; i += step) {
+            double2 acc = reinterpret_cast<const double2*>(kv)[i];
+            P2 zv[NV];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) zv[u] = reinterpret_cast<const P2*>(Z + u * ld)[i];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) {
+                acc.x = fma(coef[u], (double)zv[u].x, acc.x);
+                acc.y = fma(coef[u], (double)zv[u].y, acc.y);
+            }
+            reinterpret_cast<double2*>(kv)[i] = acc;
+        }
+        if ((n & 1) && tid == 0) {
+            double acc = kv[n - 1];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) acc = fma(coef[u], (double)Z[u * ld + n - 1], acc);
+            kv[n - 1] = acc;
+        }
+    } else {
+        for (long long i = tid; i < n; i += step) {
+            double acc = kv[i];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) acc = fma(coef[u], (double)Z[u * ld + i], acc);
+            kv[i] = acc;
+        }
     }
 }
 
@@ -547,17 +654,51 @@ hipError_t launch_rhs_mix(const double* G, const double* w, double* out, const d
     return hipGetLastError();
 }
 
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w, long long n, int self,
                        double* part, int nblocks, hipStream_t st) {
-    dots_kernel<<<nblocks, kBlock, 0, st>>>(X, nvec, ld, w, n, self, part);
-    return hipGetLastError();
+    const int nout = nvec + self;
+    const bool v2 = aligned16(w) && (nvec == 0 || (aligned16(X) && ld % 2 == 0));
+    if (nvec == 0) {
+        if (v2) dots_kernel<0, true><<<nblocks, kBlock, 0, st>>>(X, ld, w, n, self, part, nout, 0);
+        else dots_kernel<0, false><<<nblocks, kBlock, 0, st>>>(X, ld, w, n, self, part, nout, 0);
+        return hipGetLastError();
+    }
+    for (int l0 = 0; l0 < nvec; l0 += kChunk) {
+        const int nv = std::min(kChunk, nvec - l0);
+        const int sf = (self && l0 + nv == nvec) ? 1 : 0;
+        const double* Xc = X + (long long)l0 * ld;
+        hipError_t e = dispatch_nv(nv, [&](auto NV) {
+            if (v2) dots_kernel<NV, true><<<nblocks, kBlock, 0, st>>>(Xc, ld, w, n, sf, part, nout, l0);
+            else dots_kernel<NV, false><<<nblocks, kBlock, 0, st>>>(Xc, ld, w, n, sf, part, nout, l0);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, const double* sig,
                             const double* w, double* out, long long n, double* norm_part, int nblocks,
                             hipStream_t st) {
-    gs_update_kernel<<<nblocks, kBlock, 0, st>>>(X, nvec, ld, h, sig, w, out, n, norm_part);
-    return hipGetLastError();
+    const bool v2 = aligned16(X) && aligned16(w) && aligned16(out) && ld % 2 == 0;
+    if (nvec <= 0) return hipErrorInvalidValue;
+    for (int l0 = 0; l0 < nvec; l0 += kChunk) {
+        const int nv = std::min(kChunk, nvec - l0);
+        const bool last = l0 + nv == nvec;
+        const double* Xc = X + (long long)l0 * ld;
+        const double* src = l0 == 0 ? w : out;
+        const double* sc = sig ? sig + l0 : nullptr;
+        double* np = last ? norm_part : nullptr;
+        hipError_t e = dispatch_nv(nv, [&](auto NV) {
+            if (v2) gs_update_kernel<NV, true><<<nblocks, kBlock, 0, st>>>(Xc, ld, h + l0, sc, src, out, n, np);
+            else gs_update_kernel<NV, false><<<nblocks, kBlock, 0, st>>>(Xc, ld, h + l0, sc, src, out, n, np);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_reduce(const double* part, int nblocks, int nout, double* out, int accumulate,
@@ -573,11 +714,27 @@ hipError_t launch_normalize(double* v, const double* w, const double* nrm2, long
 
 hipError_t launch_combine(double* kv, int dtype_z, const void* Z, int nz, long long ld, const double* y,
                           long long n, hipStream_t st) {
-    if (dtype_z == RK_FP64)
-        combine_kernel<double><<<grid_for(n), kBlock, 0, st>>>(kv, (const double*)Z, nz, ld, y, n);
-    else
-        combine_kernel<float><<<grid_for(n), kBlock, 0, st>>>(kv, (const float*)Z, nz, ld, y, n);
-    return hipGetLastError();
+    const size_t es = dtype_z == RK_FP64 ? 8 : 4;
+    const bool v2 = aligned16(kv) && (reinterpret_cast<uintptr_t>(Z) % (2 * es)) == 0 && ld % 2 == 0;
+    const int nb = grid_for(n / 2 + 1);
+    for (int l0 = 0; l0 < nz; l0 += kChunk) {
+        const int nv = std::min(kChunk, nz - l0);
+        const char* Zc = static_cast<const char*>(Z) + (size_t)l0 * ld * es;
+        hipError_t e = dispatch_nv(nv, [&](auto NV) {
+            if (dtype_z == RK_FP64) {
+                const double* z = reinterpret_cast<const double*>(Zc);
+                if (v2) combine_kernel<NV, double, true><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, n);
+                else combine_kernel<NV, double, false><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, n);
+            } else {
+                const float* z = reinterpret_cast<const float*>(Zc);
+                if (v2) combine_kernel<NV, float, true><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, n);
+                else combine_kernel<NV, float, false><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, n);
+            }
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_stage_combine(double* y, const double* kv, const double* b, double tau, int Q,

@@ -108,7 +108,7 @@ struct OpArgs {
     int tiles_x, tiles_y, chunks_z, nwork, per_xcd;
     int cz;                                       // elements per z-chunk
     int xo_zero;
-    T ca, cb;
+    T ca, cb, icb;                                // Chebyshev coefficients, icb = 1/cb
     T alpha[RK_MAX_Q], beta[RK_MAX_Q];            // per-stage scales
 };
 
@@ -150,8 +150,16 @@ __device__ __forceinline__ T diag_rt(int r) {
     return d;
 }
 
+// Minimum waves per SIMD requested from the register allocator: three for
+// the fp32 Chebyshev kernel of degree <= 4 (its epilogue prefetch holds
+// 2k^2 + 3k extra values), otherwise the allocator's own choice.
+template <int K, typename T, int EPI>
+struct MinWaves {
+    static constexpr int v = (sizeof(T) == 4 && EPI == EPI_CHEB && K <= 4) ? 3 : 1;
+};
+
 template <int K, typename T, int MIX, int EPI>
-__global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
+__global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kernel(OpArgs<T> p) {
     using TL = Tile<K>;
     constexpr int P = K + 1;
     constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, RX = TL::RX, RY = TL::RY;
@@ -187,8 +195,11 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
     const int gx = X0 + tx, gy0 = Y0 + py * K;
     // vs may alias p.xo (in-place Chebyshev update), so it is not restrict.
     T* vs = p.v + (long long)s * p.stride;
-    // 32-bit in-plane offset of this thread's first pencil node
+    // 32-bit in-plane offset of this thread's first pencil node, and the same
+    // in bytes (N^2 sizeof(T) < 2^32): accesses are a uniform 64-bit plane or
+    // row base plus a 32-bit per-lane byte offset
     const unsigned colbase = (unsigned)gy0 * (unsigned)N + (unsigned)gx;
+    const unsigned colbyte = colbase * (unsigned)sizeof(T);
 
     // Tiles that own only far-boundary nodes: write the zeros and leave.
     if (X0 >= nK || Y0 >= nK || Z0 >= nK) {
@@ -208,7 +219,7 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
     const T* __restrict__ us = p.u + (long long)s * p.stride;
     const T* __restrict__ us2 = MIX == MIX_PAIR ? p.u2 + (long long)s * p.stride : nullptr;
 
-    // Load slots of this thread: in-plane offset and validity (interior in x, y).
+    // Load slots of this thread: in-plane byte offset and validity (interior in x, y).
     unsigned soff[NSLOT];
     unsigned smask = 0;
 #pragma unroll
@@ -217,7 +228,7 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
         const int r = i / RX, c = i - r * RX;
         const int xx = X0 - K + c, yy = Y0 - K + r;
         const bool ok = i < RY * RX && xx > 0 && xx < nK && yy > 0 && yy < nK;
-        soff[m] = ok ? (unsigned)yy * (unsigned)N + (unsigned)xx : 0u;
+        soff[m] = ok ? ((unsigned)yy * (unsigned)N + (unsigned)xx) * (unsigned)sizeof(T) : 0u;
         smask |= ok ? (1u << m) : 0u;
     }
     T pre[NU][NSLOT];
@@ -226,17 +237,17 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
     // interior) and selects zero afterwards.
     auto issue = [&](int z) __attribute__((always_inline)) {
         if (z > 0 && z < nK) {
-            const T* __restrict__ pl = us + z * NN;
+            const char* __restrict__ pl = reinterpret_cast<const char*>(us + z * NN);
 #pragma unroll
             for (int m = 0; m < NSLOT; ++m) {
-                const T vv = pl[soff[m]];
+                const T vv = *reinterpret_cast<const T*>(pl + soff[m]);
                 pre[0][m] = (smask >> m & 1u) ? vv : T(0);
             }
             if (MIX == MIX_PAIR) {
-                const T* __restrict__ pl2 = us2 + z * NN;
+                const char* __restrict__ pl2 = reinterpret_cast<const char*>(us2 + z * NN);
 #pragma unroll
                 for (int m = 0; m < NSLOT; ++m) {
-                    const T vv = pl2[soff[m]];
+                    const T vv = *reinterpret_cast<const T*>(pl2 + soff[m]);
                     pre[NU - 1][m] = (smask >> m & 1u) ? vv : T(0);
                 }
             }
@@ -358,23 +369,91 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
         if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(d);
         else return T(1) / d;
     };
-    // Jacobi diagonal of the block operator at node (c, a) of the pencil
-    auto jac = [&](auto cm, auto am) __attribute__((always_inline)) {
+    // Jacobi diagonal of the block operator at node (c, a) of the pencil:
+    //   D = alpha dMx dMy dMz + beta (dKx dMy dMz + dMx dKy dMz + dMx dMy dKz)
+    //     = C1 (alpha dMx + beta dKx) + C2 beta dMx,
+    // C1 = dMy dMz and C2 = dKy dMz + dMy dKz compile-time constants; the
+    // per-thread factors may carry a common scale.
+    auto jac_s = [&](auto cm, auto am, T u1, T u2) __attribute__((always_inline)) {
         constexpr int c = decltype(cm)::value;
         constexpr int a = decltype(am)::value;
-        constexpr T dmy = T(DG<K, 0, a>::v), dky = T(DG<K, 1, a>::v);
-        constexpr T dmz = T(DG<K, 0, c>::v), dkz = T(DG<K, 1, c>::v);
-        const T dM = dmx * (dmy * dmz);
-        const T dK = dkx * (dmy * dmz) + dmx * (dky * dmz + dmy * dkz);
-        return fma(alpha, dM, beta * dK);
+        constexpr T C1 = T(DG<K, 0, a>::v * DG<K, 0, c>::v);
+        constexpr T C2 = T(DG<K, 1, a>::v * DG<K, 0, c>::v + DG<K, 0, a>::v * DG<K, 1, c>::v);
+        return fma(C1, u1, C2 * u2);
     };
+    const T ju1 = fma(alpha, dmx, beta * dkx), ju2 = beta * dmx;
+    auto jac = [&](auto cm, auto am) __attribute__((always_inline)) { return jac_s(cm, am, ju1, ju2); };
 
+    const int E1 = min(E0 + CZ, n);                    // chunk elements E0 .. E1-1
     // Pencils whose nodes are all interior in x and y take the branch-free path.
     const bool pencil_inner = colok && !xbnd && gy0 > 0 && gy0 + K - 1 < nK;
+    // Entry of a vector at this thread's column in the row that starts at
+    // element offset ro (uniform 64-bit row base + 32-bit lane byte offset).
+    auto at = [&](const T* base, long long ro) __attribute__((always_inline)) -> const T& {
+        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base + ro) + colbyte);
+    };
+    // Epilogue prefetch (fp32 march, residual and Chebyshev epilogues): the
+    // epilogue inputs of output plane c of an element are fetched in the
+    // iteration that x-passes that plane and folded into epre[c] in the next
+    // one, so epre is complete when the element is written and the writes
+    // wait on no load.  x itself comes from the staged plane in LDS (no second
+    // read from memory).  For the Chebyshev update
+    //   out = x + ca (x - x_prev) + cb D^-1 (b - A x) = (cb / D) (epre - A x),
+    //   epre = b + (x + ca (x - x_prev)) D / cb;
+    // for the residual epre = b.
+    constexpr bool PF = EPI != EPI_STORE && NBUF == 2 && K <= 4;   // registers allow it up to Q_4
+    T epre[PF ? K : 1][K];
+    T fb[K], fx[K], fo[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) { fb[a] = T(0); fx[a] = T(0); fo[a] = T(0); }
+    const T pu1 = ju1 * p.icb, pu2 = ju2 * p.icb;       // D / cb factors
+    // fetch the epilogue inputs of output plane c of element ee, whose input
+    // plane is staged in sU[buf] (fast-path lanes of flushed elements only)
+    auto pf_issue = [&](int ee, int c, int buf) __attribute__((always_inline)) {
+        if (pencil_inner && ee >= E0 && ee > 0 && ee < E1) {
+            const long long zo = (long long)(ee * K + c) * NN;
+            const T* U = sU + buf * USZ + (py * K + K) * RX + tx + K;
+            cfor<K>([&](auto am) {
+                constexpr int a = decltype(am)::value;
+                const long long ro = zo + (long long)a * N;
+                fb[a] = at(bs, ro);
+                if (EPI == EPI_CHEB) {
+                    fx[a] = U[a * RX];
+                    fo[a] = xos ? at(xos, ro) : T(0);
+                }
+            });
+        }
+    };
+    // fold the inputs fetched for output plane c into epre[c]
+    auto pf_fold = [&](auto cm) __attribute__((always_inline)) {
+        constexpr int c = decltype(cm)::value;
+        if constexpr (PF) {
+            cfor<K>([&](auto am) {
+                constexpr int a = decltype(am)::value;
+                if (EPI == EPI_RESID) epre[c][a] = fb[a];
+                else epre[c][a] = fma(fma(p.ca, fx[a] - fo[a], fx[a]), jac_s(cm, am, pu1, pu2), fb[a]);
+            });
+        }
+    };
+
     // Write the K completed output planes of element e.  Per output plane the
     // epilogue loads of its K nodes are issued together before any use.
     auto flush = [&](int e) __attribute__((always_inline)) {
-        if (pencil_inner && e > 0) {
+        if (PF && pencil_inner && e > 0) {
+            cfor<K>([&](auto cm) {
+                constexpr int c = decltype(cm)::value;
+                const long long zo = (long long)(e * K + c) * NN;
+                cfor<K>([&](auto am) {
+                    constexpr int a = decltype(am)::value;
+                    const long long ro = zo + (long long)a * N;
+                    const T d = epre[PF ? c : 0][a] - acc[c][a];
+                    const T out = EPI == EPI_RESID ? d : p.cb * recip(jac(cm, am)) * d;
+                    *reinterpret_cast<T*>(reinterpret_cast<char*>(vs + ro) + colbyte) = out;
+                });
+            });
+            return;
+        }
+        if (!PF && pencil_inner && e > 0) {
             cfor<K>([&](auto cm) {
                 constexpr int c = decltype(cm)::value;
                 const long long zo = (long long)(e * K + c) * NN;
@@ -383,10 +462,10 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
                     cfor<K>([&](auto am) {
                         constexpr int a = decltype(am)::value;
                         const long long ro = zo + (long long)a * N;
-                        lb[a] = (bs + ro)[colbase];
+                        lb[a] = at(bs, ro);
                         if (EPI == EPI_CHEB) {
-                            lx[a] = (us + ro)[colbase];
-                            lo[a] = xos ? (xos + ro)[colbase] : T(0);
+                            lx[a] = at(us, ro);
+                            lo[a] = xos ? at(xos, ro) : T(0);
                         }
                     });
                 }
@@ -398,7 +477,7 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
                     if (EPI == EPI_STORE) out = av;
                     else if (EPI == EPI_RESID) out = lb[a] - av;
                     else out = lx[a] + p.ca * (lx[a] - lo[a]) + p.cb * (lb[a] - av) * recip(jac(cm, am));
-                    (vs + ro)[colbase] = out;
+                    *reinterpret_cast<T*>(reinterpret_cast<char*>(vs + ro) + colbyte) = out;
                 });
             });
             return;
@@ -432,69 +511,120 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
         });
     };
 
-    // z-accumulation of the plane just y-passed (plane index b within the
-    // current element e); flush when the element's top plane has arrived.
-    int e = 0, b = 0;
-    auto zstep = [&](bool first) __attribute__((always_inline)) {
-        if (first) {
+    // z-accumulation of the plane just y-passed.  B is the plane's index
+    // within the current element e (compile time: the march is unrolled by
+    // element, so no accumulator is selected at run time); B = 0 starts the
+    // first element of the chunk.  When the element's top plane (B = K) has
+    // been added, its K output planes are written and the top plane's
+    // contribution carries over as the bottom plane of element e+1.
+    int e = 0;
+    auto zplane = [&](auto bm) __attribute__((always_inline)) {
+        constexpr int B = decltype(bm)::value;
+        if constexpr (B == 0) {
             zinit();
         } else {
-            cfor<K>([&](auto bm) {
-                constexpr int B = decltype(bm)::value + 1;
-                if (b == B) zacc(std::integral_constant<int, B>{});
-            });
-        }
-        if (b == K) {
-            if (e >= E0) flush(e);
-            // the top plane of element e is the bottom plane of element e+1
-            T carry[K];
+            // this plane is output plane B of element e (B < K) or plane 0 of e+1
+            if constexpr (PF && B < K) pf_fold(bm);
+            zacc(bm);
+            if constexpr (B == K) {
+                if (e >= E0) flush(e);
+                T carry[K];
 #pragma unroll
-            for (int a = 0; a < K; ++a) carry[a] = acc[K][a];
-            zinit();
+                for (int a = 0; a < K; ++a) carry[a] = acc[K][a];
+                zinit();
 #pragma unroll
-            for (int a = 0; a < K; ++a) acc[0][a] += carry[a];
-            ++e;
-            b = 0;
+                for (int a = 0; a < K; ++a) acc[0][a] += carry[a];
+                ++e;
+                if constexpr (PF) pf_fold(std::integral_constant<int, 0>{});
+            }
         }
-        ++b;
+    };
+    // after zplane(B) (plane eK+B, or eK with e advanced when B = K): fetch
+    // the epilogue inputs of the next plane, staged in sU[buf]
+    auto pf_next = [&](auto bm, int buf) __attribute__((always_inline)) {
+        constexpr int B = decltype(bm)::value;
+        constexpr int CN = (B == K || B == 0) ? 1 : B + 1;
+        if constexpr (PF) {
+            if constexpr (CN == K) pf_issue(e + 1, 0, buf);
+            else pf_issue(e, CN, buf);
+        }
     };
 
-    // March up the chunk over the planes zbeg .. zend, each processed once.
-    const int E1 = min(E0 + CZ, n);
+    // March up the chunk over the planes zbeg .. zend (NP = NE K + 1 planes,
+    // NE >= 1 elements), each processed once.  Plane p >= 1 has index
+    // B = (p - 1) mod K + 1 within its element; the last plane has B = K.
     const int ebeg = E0 > 0 ? E0 - 1 : 0;
-    const int zbeg = ebeg * K, zend = E1 * K;
-    const int NP = zend - zbeg + 1;
+    const int NE = E1 - ebeg;
+    const int zbeg = ebeg * K;
+    const int NP = NE * K + 1;
     e = ebeg;
-    if (NBUF == 2) {
+    using I0 = std::integral_constant<int, 0>;
+    using IK = std::integral_constant<int, K>;
+    if constexpr (NBUF == 2) {
         // Iteration q: y-pass + z-accumulation of plane q-1, x-pass of plane
         // q, staging of plane q+1 (loaded during iteration q-1), loads of
         // plane q+2; then one barrier.  The phases use disjoint buffers.
-        issue(zbeg);
-        commit(0);
-        if (NP > 1) issue(zbeg + 1);
-        __syncthreads();
-        xpass(0);
-        if (NP > 1) {
-            commit(1);
-            if (NP > 2) issue(zbeg + 2);
-        }
-        __syncthreads();
-        for (int q = 1; q < NP; ++q) {
+        auto iter = [&](int q, auto bm) __attribute__((always_inline)) {
+            // q is kept opaque (an empty asm in a scalar register): otherwise
+            // the buffer parity folds to a constant in each unrolled copy and
+            // every copy keeps its own LDS addresses live (more VGPRs).
+            asm volatile("" : "+s"(q));
             ypass((q - 1) & 1);
-            zstep(q == 1);
+            zplane(bm);
+            pf_next(bm, q & 1);
             xpass(q & 1);
             if (q + 1 < NP) {
                 commit((q + 1) & 1);
                 if (q + 2 < NP) issue(zbeg + q + 2);
             }
             __syncthreads();
+        };
+        issue(zbeg);
+        commit(0);
+        issue(zbeg + 1);
+        __syncthreads();
+        xpass(0);
+        commit(1);
+        if (NP > 2) issue(zbeg + 2);
+        __syncthreads();
+        iter(1, I0{});
+        for (int g = 0; g < NE; ++g) {
+            cfor<K>([&](auto bm) {
+                constexpr int B = decltype(bm)::value + 1;
+                const int q = 2 + g * K + (B - 1);
+                if (q < NP) iter(q, std::integral_constant<int, B>{});
+            });
         }
         ypass((NP - 1) & 1);
-        zstep(NP == 1);
+        zplane(IK{});
     } else {
         // Iteration q: stage plane q (loaded during iteration q-1), loads of
         // plane q+1, y-pass + z-accumulation of plane q-1; barrier; x-pass of
-        // plane q; barrier.
+        // plane q; barrier.  (fp64 keeps a run-time plane index: the unrolled
+        // march needs more registers here and costs occupancy.)
+        int b = 0;
+        auto zstep = [&](bool first) __attribute__((always_inline)) {
+            if (first) {
+                zinit();
+            } else {
+                cfor<K>([&](auto bm) {
+                    constexpr int B = decltype(bm)::value + 1;
+                    if (b == B) zacc(std::integral_constant<int, B>{});
+                });
+            }
+            if (b == K) {
+                if (e >= E0) flush(e);
+                T carry[K];
+#pragma unroll
+                for (int a = 0; a < K; ++a) carry[a] = acc[K][a];
+                zinit();
+#pragma unroll
+                for (int a = 0; a < K; ++a) acc[0][a] += carry[a];
+                ++e;
+                b = 0;
+            }
+            ++b;
+        };
         issue(zbeg);
         for (int q = 0; q < NP; ++q) {
             commit(0);
@@ -508,7 +638,7 @@ __global__ void __launch_bounds__(Tile<K>::NT) op_kernel(OpArgs<T> p) {
             __syncthreads();
         }
         ypass(0);
-        zstep(NP == 1);
+        zstep(false);
     }
     // The chunk that contains the top boundary plane writes it.
     if (E0 + CZ > n && colok) {
@@ -547,6 +677,7 @@ hipError_t launch_op_typed(const OpLaunch& L) {
     p.xo_zero = L.xo == nullptr;
     p.ca = T(L.ca);
     p.cb = T(L.cb);
+    p.icb = L.cb != 0.0 ? T(1.0 / L.cb) : T(0);
     for (int i = 0; i < RK_MAX_Q; ++i) {
         p.alpha[i] = T(L.alpha[i]);
         p.beta[i] = T(L.beta[i]);

@@ -104,8 +104,9 @@ struct rk_ctx {
     Coeffs form[F_NFORMS];         // fine-level operator coefficients
     void* tmp1 = nullptr;
     void* tmp2 = nullptr;
-    double* V = nullptr;           // (restart+1) x Q N3
-    double* Z = nullptr;           // restart x Q N3
+    long long ld = 0;              // stride of the Krylov vectors (Q N3 padded to 256 bytes)
+    double* V = nullptr;           // (restart+1) x ld
+    double* Z = nullptr;           // restart x ld
     double* w = nullptr;           // Q N3
     double* kv = nullptr;          // Q N3
     double* rhs = nullptr;         // Q N3
@@ -204,8 +205,10 @@ size_t carve(rk_ctx& c, char* base) {
     c.tmp2 = cv.take(pcs * Q * tmp);
     const long long qn = (long long)Q * c.N3;
     const int m = c.opt.restart;
-    c.V = (double*)cv.take(8 * (size_t)(m + 1) * qn);
-    c.Z = (double*)cv.take(8 * (size_t)m * qn);
+    // Krylov vectors are qn long, stored at a stride padded to 256 bytes
+    c.ld = (qn + 31) / 32 * 32;
+    c.V = (double*)cv.take(8 * (size_t)(m + 1) * c.ld);
+    c.Z = (double*)cv.take(8 * (size_t)m * c.ld);
     c.w = (double*)cv.take(8 * qn);
     c.kv = (double*)cv.take(8 * qn);
     c.rhs = (double*)cv.take(8 * qn);
@@ -225,8 +228,10 @@ int setup_sizes(rk_ctx& c, const rk_mesh* mesh, int degree, int Q, const rk_opti
     if (!mesh || mesh->n_cells < 1 || degree < 1 || degree > RK_MAX_DEGREE || Q < 1 || Q > RK_MAX_Q)
         return fail(nullptr, RK_EINVAL, "mesh, degree (1..6) or Q (1..9) out of range");
     // launch grids put (stage, z-plane) pairs in one grid dimension (<= 65535)
-    if ((long long)mesh->n_cells * degree + 1 > 65535 / Q)
-        return fail(nullptr, RK_EINVAL, "grid too large: (n_cells * degree + 1) * Q must not exceed 65535");
+    // and operator kernels address a node plane with 32-bit byte offsets
+    if ((long long)mesh->n_cells * degree + 1 > std::min(65535 / Q, 16384))
+        return fail(nullptr, RK_EINVAL, "grid too large: need (n_cells*degree + 1) <= 16384 and "
+                                        "(n_cells*degree + 1) * Q <= 65535");
     if (opt) c.opt = *opt;
     else rk_default_options(&c.opt);
     std::string msg;
@@ -500,11 +505,11 @@ int estimate_eigs(rk_ctx* c) {
 int arnoldi_orth(rk_ctx* c, int j, double* hcol) {
     const long long qn = (long long)c->Q * c->N3;
     const int nv = j + 1;
-    double* Vn = c->V + (long long)nv * qn;
+    double* Vn = c->V + (long long)nv * c->ld;
     double* hs = c->host_scal.data();
-    HIPCHK(c, launch_dots(c->V, nv, qn, c->w, qn, 1, c->part, kRedBlocks, c->stream));
+    HIPCHK(c, launch_dots(c->V, nv, c->ld, c->w, qn, 1, c->part, kRedBlocks, c->stream));
     HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv + 1, c->scal, 0, c->stream, c->sig, nv));
-    HIPCHK(c, launch_gs_update(c->V, nv, qn, c->scal, c->sig, c->w, Vn, qn, c->part, kRedBlocks, c->stream));
+    HIPCHK(c, launch_gs_update(c->V, nv, c->ld, c->scal, c->sig, c->w, Vn, qn, c->part, kRedBlocks, c->stream));
     HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream, nullptr, 0, c->sig + nv));
     HIPCHK(c, hipMemcpyAsync(hs, c->scal, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -512,9 +517,9 @@ int arnoldi_orth(rk_ctx* c, int j, double* hcol) {
     const double w2 = hs[nv];
     double nrm2 = hs[nv + 1];
     if (nrm2 < 1e-4 * w2) {
-        HIPCHK(c, launch_dots(c->V, nv, qn, Vn, qn, 0, c->part, kRedBlocks, c->stream));
+        HIPCHK(c, launch_dots(c->V, nv, c->ld, Vn, qn, 0, c->part, kRedBlocks, c->stream));
         HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv, c->scal2, 0, c->stream, c->sig, nv));
-        HIPCHK(c, launch_gs_update(c->V, nv, qn, c->scal2, c->sig, Vn, Vn, qn, c->part, kRedBlocks, c->stream));
+        HIPCHK(c, launch_gs_update(c->V, nv, c->ld, c->scal2, c->sig, Vn, Vn, qn, c->part, kRedBlocks, c->stream));
         HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream, nullptr, 0, c->sig + nv));
         HIPCHK(c, hipMemcpyAsync(hs, c->scal2, sizeof(double) * nv, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemcpyAsync(hs + nv + 1, c->scal + nv + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -737,11 +742,11 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
         g[0] = rnorm;
         int jd = 0;
         for (int j = 0; j < m && its < c->opt.max_iter; ++j) {
-            rc = precondition(c, c->V + (long long)j * qn, c->Z + (long long)j * qn, (double*)c->mbuf,
+            rc = precondition(c, c->V + (long long)j * c->ld, c->Z + (long long)j * c->ld, (double*)c->mbuf,
                               c->sig + j);
             if (rc) return rc;
             vcyc += c->opt.mode == RK_BATCHED ? 1 : Q;
-            rc = apply_cala(c, c->Z + (long long)j * qn, (const double*)c->mbuf, c->w, nullptr);
+            rc = apply_cala(c, c->Z + (long long)j * c->ld, (const double*)c->mbuf, c->w, nullptr);
             if (rc) return rc;
             {
                 Timer t(c, C_REST);
@@ -781,7 +786,7 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
             Timer t(c, C_REST);
             HIPCHK(c, hipMemcpyAsync(c->ycoef, yv.data(), sizeof(double) * jd, hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
-            HIPCHK(c, launch_combine(c->kv, RK_FP64, c->Z, jd, qn, c->ycoef, qn, c->stream));
+            HIPCHK(c, launch_combine(c->kv, RK_FP64, c->Z, jd, c->ld, c->ycoef, qn, c->stream));
         }
         // true residual r = rhs - A k
         HIPCHK(c, launch_stage_mix(RK_FP64, c->kv, RK_FP64, c->mbuf, c->mix + kMixAinv, Q, Q, c->N, c->stream));
