@@ -379,24 +379,8 @@ int prolong_add(rk_ctx* c, int l, int s0, int ns, const void* coarse, void* fine
     Level& F = c->lv[l];
     Level& C = c->lv[l + 1];
     const size_t es = dsize(c->pc);
-    const int nf = F.N, nc = C.N;
-    TransferLaunch T;
-    T.k = c->k; T.dtype = c->pc; T.restrict_ = false; T.nstage = ns; T.stream = c->stream;
-    // z: (nc,nc,nc) -> (nc,nc,nf)
-    T.axis = 2; T.add = false; T.in = (const char*)coarse + es * s0 * C.N3; T.out = c->tmp1;
-    T.din[0] = nc; T.din[1] = nc; T.din[2] = nc; T.dout[0] = nc; T.dout[1] = nc; T.dout[2] = nf;
-    T.sin = C.N3; T.sout = (long long)nc * nc * nf;
-    HIPCHK(c, launch_transfer(T));
-    // y: (nc,nc,nf) -> (nc,nf,nf)
-    T.axis = 1; T.in = c->tmp1; T.out = c->tmp2;
-    T.din[0] = nc; T.din[1] = nc; T.din[2] = nf; T.dout[0] = nc; T.dout[1] = nf; T.dout[2] = nf;
-    T.sin = (long long)nc * nc * nf; T.sout = (long long)nc * nf * nf;
-    HIPCHK(c, launch_transfer(T));
-    // x: (nc,nf,nf) -> (nf,nf,nf), added
-    T.axis = 0; T.add = true; T.in = c->tmp2; T.out = (char*)fine + es * s0 * F.N3;
-    T.din[0] = nc; T.din[1] = nf; T.din[2] = nf; T.dout[0] = nf; T.dout[1] = nf; T.dout[2] = nf;
-    T.sin = (long long)nc * nf * nf; T.sout = F.N3;
-    HIPCHK(c, launch_transfer(T));
+    HIPCHK(c, launch_prolong_add(c->k, c->pc, (const char*)coarse + es * s0 * C.N3,
+                                 (char*)fine + es * s0 * F.N3, C.n, ns, C.N3, F.N3, c->stream));
     return RK_OK;
 }
 

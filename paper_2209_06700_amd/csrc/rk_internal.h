@@ -90,6 +90,10 @@ struct TransferLaunch {
     hipStream_t stream = nullptr;
 };
 hipError_t launch_transfer(const TransferLaunch& L);
+// fine += P coarse for stages [0, nstage): coarse grid of nc cells (stage
+// stride cstride), fine grid of 2 nc cells (stride fstride), degree k; one pass
+hipError_t launch_prolong_add(int k, int dtype, const void* coarse, void* fine, int nc, int nstage,
+                              long long cstride, long long fstride, hipStream_t st);
 
 // x = cb D^-1 b (first Chebyshev step from a zero start), D = diag of the
 // diagonal-mix operator with scales sc, per stage; boundary entries 0.
