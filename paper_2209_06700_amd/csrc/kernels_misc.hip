@@ -1,7 +1,6 @@
-// Streaming kernels: multigrid transfers, Chebyshev start, stage mixes
-// (basis changes, right-hand side), Krylov vector operations, reductions and
-// the stage combination.  All are bandwidth-bound grid-stride kernels with
-// coalesced x-fastest access.
+// Streaming kernels: Chebyshev start, stage mixes (basis changes, right-hand
+// side), Krylov vector operations, reductions and the stage combination.  All
+// are bandwidth-bound with coalesced x-fastest access.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,7 +18,6 @@ constexpr int kMP = RK_MAX_DEGREE + 1;
 
 // Element tables of every degree for kernels that index them at run time.
 struct AllTables {
-    double P[kMP][(2 * RK_MAX_DEGREE + 1) * kMP];   // prolongation, row-major (2k+1) x (k+1)
     double dM[kMP][kMP];                            // 1D global mass diagonal by local index
     double dA[kMP][kMP];                            // 1D global stiffness diagonal by local index
 };
@@ -27,8 +25,6 @@ struct AllTables {
 template <int K>
 constexpr void fill_tables(AllTables& t) {
     constexpr auto d = elem::make<K>();
-    for (int f = 0; f <= 2 * K; ++f)
-        for (int c = 0; c <= K; ++c) t.P[K][f * (K + 1) + c] = d.P[f][c];
     for (int r = 0; r < K; ++r) {
         t.dM[K][r] = r == 0 ? d.M[0][0] + d.M[K][K] : d.M[r][r];
         t.dA[K][r] = r == 0 ? d.A[0][0] + d.A[K][K] : d.A[r][r];
@@ -64,94 +60,6 @@ inline int grid_for(long long n, int cap = 8192) {
     long long g = (n + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
     return (int)(g > cap ? cap : g);
-}
-
-// ---------------------------------------------------------------------------
-// Multigrid transfer, one 1D pass along `axis` of the tensor-product
-// prolongation P = P1 (x) P1 (x) P1 or its transpose (restriction).
-// P1 is the global 1D interpolation from the n-cell to the 2n-cell partition;
-// within coarse cell E the fine nodes 2Ek + j (j = 0..2k) take
-// sum_a Pe[j][a] x_c[Ek + a].
-// ---------------------------------------------------------------------------
-template <int K, typename T, bool RESTRICT, bool ADD>
-__global__ void __launch_bounds__(kBlock) transfer_kernel(const T* __restrict__ in, T* __restrict__ out,
-                                                        int ax, int dox, int doy, int doz,
-                                                        int dix, int diy, long long sin,
-                                                        long long sout, int nstage) {
-    constexpr int P = K + 1;
-    const double* Pe = kTab.P[K];
-    const long long per = (long long)dox * doy * doz;
-    const long long total = per * nstage;
-    const long long in_plane = (long long)dix * diy;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const int s = (int)(idx / per);
-        long long r = idx - (long long)s * per;
-        const int oz = (int)(r / ((long long)dox * doy));
-        r -= (long long)oz * dox * doy;
-        const int oy = (int)(r / dox);
-        const int ox = (int)(r - (long long)oy * dox);
-        int o[3] = {ox, oy, oz};
-        const int dlen = ax == 0 ? dox : (ax == 1 ? doy : doz);   // output length on axis
-        const long long istep = ax == 0 ? 1 : (ax == 1 ? dix : in_plane);
-        const int pos = o[ax];
-        o[ax] = 0;
-        const long long ibase = (long long)s * sin + o[0] + (long long)o[1] * dix + (long long)o[2] * in_plane;
-        T val = T(0);
-        if (RESTRICT) {
-            // coarse node pos = E k + a; dlen = coarse length
-            const int nc = (dlen - 1) / K;
-            if (pos > 0 && pos < dlen - 1) {
-                const int E = pos / K, a = pos - E * K;
-                if (a == 0) {
-                    // vertex: column k of coarse cell E-1 and column 0 of cell E
-                    const long long f0 = 2LL * (E - 1) * K;
-#pragma unroll
-                    for (int j = 0; j <= 2 * K; ++j) val = fma(T(Pe[j * P + K]), in[ibase + (f0 + j) * istep], val);
-                    if (E < nc) {
-                        const long long f1 = 2LL * E * K;
-#pragma unroll
-                        for (int j = 1; j <= 2 * K; ++j) val = fma(T(Pe[j * P]), in[ibase + (f1 + j) * istep], val);
-                    }
-                } else {
-                    const long long f0 = 2LL * E * K;
-#pragma unroll
-                    for (int j = 0; j <= 2 * K; ++j) val = fma(T(Pe[j * P + a]), in[ibase + (f0 + j) * istep], val);
-                }
-            }
-        } else {
-            // fine node pos = 2 E k + j
-            if (pos > 0 && pos < dlen - 1) {
-                int E = pos / (2 * K), j = pos - E * 2 * K;
-                const long long c0 = (long long)E * K;
-#pragma unroll
-                for (int a = 0; a <= K; ++a) val = fma(T(Pe[j * P + a]), in[ibase + (c0 + a) * istep], val);
-            }
-        }
-        const long long oidx = (long long)s * sout + ox + (long long)oy * dox + (long long)oz * dox * doy;
-        if (ADD) out[oidx] += val;
-        else out[oidx] = val;
-    }
-}
-
-template <int K, typename T>
-hipError_t transfer_typed(const TransferLaunch& L) {
-    const long long total = (long long)L.dout[0] * L.dout[1] * L.dout[2] * L.nstage;
-    dim3 g(grid_for(total)), b(kBlock);
-    const T* in = static_cast<const T*>(L.in);
-    T* out = static_cast<T*>(L.out);
-    if (L.restrict_)
-        transfer_kernel<K, T, true, false><<<g, b, 0, L.stream>>>(in, out, L.axis, L.dout[0], L.dout[1], L.dout[2], L.din[0], L.din[1], L.sin, L.sout, L.nstage);
-    else if (L.add)
-        transfer_kernel<K, T, false, true><<<g, b, 0, L.stream>>>(in, out, L.axis, L.dout[0], L.dout[1], L.dout[2], L.din[0], L.din[1], L.sin, L.sout, L.nstage);
-    else
-        transfer_kernel<K, T, false, false><<<g, b, 0, L.stream>>>(in, out, L.axis, L.dout[0], L.dout[1], L.dout[2], L.din[0], L.din[1], L.sin, L.sout, L.nstage);
-    return hipGetLastError();
-}
-
-template <int K>
-hipError_t transfer_k(const TransferLaunch& L) {
-    return L.dtype == RK_FP64 ? transfer_typed<K, double>(L) : transfer_typed<K, float>(L);
 }
 
 // ---------------------------------------------------------------------------
@@ -608,17 +516,6 @@ __global__ void __launch_bounds__(kBlock) random_fill_kernel(T* __restrict__ x, 
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-hipError_t launch_transfer(const TransferLaunch& L) {
-    switch (L.k) {
-        case 1: return transfer_k<1>(L);
-        case 2: return transfer_k<2>(L);
-        case 3: return transfer_k<3>(L);
-        case 4: return transfer_k<4>(L);
-        case 5: return transfer_k<5>(L);
-        case 6: return transfer_k<6>(L);
-        default: return hipErrorInvalidValue;
-    }
-}
 
 hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* b, void* x, int n,
                              int s0, int nstage, double cb, hipStream_t st) {

@@ -102,8 +102,7 @@ struct rk_ctx {
     int pc = RK_FP64;              // preconditioner dtype
     std::vector<Level> lv;
     Coeffs form[F_NFORMS];         // fine-level operator coefficients
-    void* tmp1 = nullptr;
-    void* tmp2 = nullptr;
+    void* tmp = nullptr;           // restriction intermediate
     long long ld = 0;              // stride of the Krylov vectors (Q N3 padded to 256 bytes)
     double* V = nullptr;           // (restart+1) x ld
     double* Z = nullptr;           // restart x ld
@@ -198,11 +197,11 @@ size_t carve(rk_ctx& c, char* base) {
         L.x = cv.take(pcs * Q * L.N3);
         L.y = cv.take(pcs * Q * L.N3);
     }
+    // restriction intermediate: x-y restricted fine planes of the finest pair
     size_t tmp = 1;
     for (size_t l = 0; l + 1 < c.lv.size(); ++l)
-        tmp = std::max(tmp, (size_t)c.lv[l + 1].N * c.lv[l].N * c.lv[l].N);
-    c.tmp1 = cv.take(pcs * Q * tmp);
-    c.tmp2 = cv.take(pcs * Q * tmp);
+        tmp = std::max(tmp, (size_t)c.lv[l].N * c.lv[l + 1].N * c.lv[l + 1].N);
+    c.tmp = cv.take(pcs * Q * tmp);
     const long long qn = (long long)Q * c.N3;
     const int m = c.opt.restart;
     // Krylov vectors are qn long, stored at a stride padded to 256 bytes
@@ -354,24 +353,8 @@ int restrict_to(rk_ctx* c, int l, int s0, int ns, const void* fine) {
     Level& F = c->lv[l];
     Level& C = c->lv[l + 1];
     const size_t es = dsize(c->pc);
-    const int nf = F.N, nc = C.N;
-    TransferLaunch T;
-    T.k = c->k; T.dtype = c->pc; T.restrict_ = true; T.nstage = ns; T.stream = c->stream;
-    // x: (nf,nf,nf) -> (nc,nf,nf)
-    T.axis = 0; T.in = (const char*)fine + es * s0 * F.N3; T.out = c->tmp1;
-    T.din[0] = nf; T.din[1] = nf; T.din[2] = nf; T.dout[0] = nc; T.dout[1] = nf; T.dout[2] = nf;
-    T.sin = F.N3; T.sout = (long long)nc * nf * nf;
-    HIPCHK(c, launch_transfer(T));
-    // y: (nc,nf,nf) -> (nc,nc,nf)
-    T.axis = 1; T.in = c->tmp1; T.out = c->tmp2;
-    T.din[0] = nc; T.din[1] = nf; T.din[2] = nf; T.dout[0] = nc; T.dout[1] = nc; T.dout[2] = nf;
-    T.sin = (long long)nc * nf * nf; T.sout = (long long)nc * nc * nf;
-    HIPCHK(c, launch_transfer(T));
-    // z: (nc,nc,nf) -> (nc,nc,nc)
-    T.axis = 2; T.in = c->tmp2; T.out = (char*)C.b + es * s0 * C.N3;
-    T.din[0] = nc; T.din[1] = nc; T.din[2] = nf; T.dout[0] = nc; T.dout[1] = nc; T.dout[2] = nc;
-    T.sin = (long long)nc * nc * nf; T.sout = C.N3;
-    HIPCHK(c, launch_transfer(T));
+    HIPCHK(c, launch_restrict(c->k, c->pc, (const char*)fine + es * s0 * F.N3, (char*)C.b + es * s0 * C.N3,
+                              c->tmp, C.n, ns, F.N3, C.N3, c->stream));
     return RK_OK;
 }
 

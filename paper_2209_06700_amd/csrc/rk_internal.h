@@ -74,22 +74,13 @@ struct OpLaunch {
 };
 hipError_t launch_op(const OpLaunch& L);
 
-// One 1D pass of the tensor-product transfer along `axis` (0 = x, 1 = y, 2 = z).
-//   restrict: coarse-length output along axis, fine input;  prolong: the reverse.
-struct TransferLaunch {
-    int k = 0, dtype = RK_FP64;
-    bool restrict_ = true;
-    bool add = false;          // prolong only: out += P in
-    int axis = 0;
-    const void* in = nullptr;
-    void* out = nullptr;
-    int din[3] = {0, 0, 0};    // input dims (x, y, z)
-    int dout[3] = {0, 0, 0};   // output dims
-    long long sin = 0, sout = 0;   // stage strides
-    int nstage = 1;
-    hipStream_t stream = nullptr;
-};
-hipError_t launch_transfer(const TransferLaunch& L);
+// Multigrid transfers (one fused pass each).
+// coarse = P^T fine for stages [0, nstage): fine grid of 2 nc cells (stage
+// stride fstride), coarse grid of nc cells (stride cstride), degree k; coarse
+// boundary nodes written as zero.  tmp holds nstage (2 nc k + 1)(nc k + 1)^2
+// values (x-y restricted fine planes).
+hipError_t launch_restrict(int k, int dtype, const void* fine, void* coarse, void* tmp, int nc, int nstage,
+                           long long fstride, long long cstride, hipStream_t st);
 // fine += P coarse for stages [0, nstage): coarse grid of nc cells (stage
 // stride cstride), fine grid of 2 nc cells (stride fstride), degree k; one pass
 hipError_t launch_prolong_add(int k, int dtype, const void* coarse, void* fine, int nc, int nstage,

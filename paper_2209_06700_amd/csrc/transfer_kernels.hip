@@ -12,6 +12,16 @@
 // x-y interpolants of the k+1 coarse planes of the current coarse cell for its
 // fine nodes; the 2k fine planes of the cell are then formed in registers
 // and added to the fine vector (one read and one write per fine node).
+//
+// Restriction x_coarse = P^T x_fine in two passes: restrict_xy_kernel
+// restricts every fine plane in x and y (one workgroup per plane tile, fine
+// plane plus the fine halo of one coarse cell staged in LDS), writing an
+// intermediate of coarse x-y size per fine plane; restrict_z_kernel then
+// restricts along z.  In 1D, coarse node Ek + a collects
+//   sum_{t=0}^{2k} Pe[t][a] f(2Ek + t)              (a = 1..k-1), and the vertex
+//   a = 0 also  sum_{t=0}^{2k-1} Pe[t][k] f(2(E-1)k + t),
+// each fine node counted once (the fine vertex 2Ek has Pe[0][0] = 1).  Coarse
+// boundary nodes are written as zero.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -189,6 +199,171 @@ __global__ void __launch_bounds__(PTile<K>::NT) prolong_add_kernel(ProlongArgs<T
     }
 }
 
+// out[a], a = 0..k-1, of coarse cell E from w[u] = f(2(E-1)k + u), u = 0..4k
+template <int K, typename T>
+__device__ __forceinline__ void rrow(const T* w, T* out) {
+    T o = T(PE<K, 0, K>::v) * w[0];
+    tfor<2 * K - 1>([&](auto tm) {
+        constexpr int t = decltype(tm)::value + 1;
+        o = fma(T(PE<K, t, K>::v), w[t], o);
+    });
+    tfor<2 * K + 1>([&](auto tm) {
+        constexpr int t = decltype(tm)::value;
+        o = fma(T(PE<K, t, 0>::v), w[2 * K + t], o);
+    });
+    out[0] = o;
+    tfor<K - 1>([&](auto am) {
+        constexpr int a = decltype(am)::value + 1;
+        T q = T(PE<K, 0, a>::v) * w[2 * K];
+        tfor<2 * K>([&](auto tm) {
+            constexpr int t = decltype(tm)::value + 1;
+            q = fma(T(PE<K, t, a>::v), w[2 * K + t], q);
+        });
+        out[a] = q;
+    });
+}
+
+template <int K>
+struct RTile {
+    static constexpr int CX = (32 / K) > 0 ? (32 / K) : 1;            // coarse cells in x
+    static constexpr int TX = CX * K;                                  // coarse nodes in x
+    static constexpr int CY0 = 256 / TX > 0 ? 256 / TX : 1;
+    static constexpr int CY = CY0 < CX ? CY0 : CX;                     // coarse cells in y
+    static constexpr int TY = CY * K;
+    static constexpr int NT = TX * CY;                                 // one y-pencil per thread
+    static constexpr int FX = 2 * (CX + 1) * K + 1;                    // staged fine width
+    static constexpr int FY = 2 * (CY + 1) * K + 1;                    // staged fine height
+    static constexpr int XP = TX + 1;
+};
+
+// mid[s][zf][yc][xc] = (R_y R_x fine[s][zf])[yc][xc]; grid (tiles, Nf, nstage)
+template <int K, typename T>
+__global__ void __launch_bounds__(RTile<K>::NT) restrict_xy_kernel(const T* __restrict__ fine, T* __restrict__ mid,
+                                                                   int nc, int tiles_x, long long fstride,
+                                                                   long long mstride) {
+    using TL = RTile<K>;
+    constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, FX = TL::FX, FY = TL::FY, XP = TL::XP;
+    constexpr int CX = TL::CX, J2 = 2 * K;
+    __shared__ T sF[FY * FX];
+    __shared__ T sR[FY * XP];
+    const int Nc = nc * K + 1, Nf = 2 * nc * K + 1;
+    const int itx = blockIdx.x % tiles_x, ity = blockIdx.x / tiles_x;
+    const int zf = blockIdx.y, s = blockIdx.z;
+    const int X0c = itx * TX, Y0c = ity * TY;
+    const int FX0 = 2 * X0c - J2, FY0 = 2 * Y0c - J2;     // one coarse cell below the tile
+    const int tid = threadIdx.x;
+    const T* __restrict__ src = fine + (long long)s * fstride + (long long)zf * Nf * Nf;
+    // all loads of the staged region are issued before any LDS write
+    constexpr int NS = (FY * FX + NT - 1) / NT;
+    T v[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        const int i = tid + m * NT;
+        const int r = i / FX, c = i - r * FX;
+        const int xf = FX0 + c, yf = FY0 + r;
+        const bool ok = i < FY * FX && xf >= 0 && xf < Nf && yf >= 0 && yf < Nf;
+        v[m] = ok ? src[(long long)yf * Nf + xf] : T(0);
+    }
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        const int i = tid + m * NT;
+        if (m < NS - 1 || i < FY * FX) sF[i] = v[m];
+    }
+    __syncthreads();
+    for (int it = tid; it < FY * CX; it += NT) {
+        const int cx = it / FY, r = it - cx * FY;
+        T wv[4 * K + 1], o[K];
+        const T* row = &sF[r * FX + cx * J2];
+#pragma unroll
+        for (int u = 0; u <= 4 * K; ++u) wv[u] = row[u];
+        rrow<K, T>(wv, o);
+#pragma unroll
+        for (int a = 0; a < K; ++a) sR[r * XP + cx * K + a] = o[a];
+    }
+    __syncthreads();
+    const int tx = tid % TX, py = tid / TX;
+    const int gx = X0c + tx, gy0 = Y0c + py * K;
+    if (gx == 0 || gx >= Nc - 1) return;           // boundary columns: zeroed by the z pass
+    T wv[4 * K + 1], yv[K];
+#pragma unroll
+    for (int u = 0; u <= 4 * K; ++u) wv[u] = sR[(py * J2 + u) * XP + tx];
+    rrow<K, T>(wv, yv);
+    T* dst = mid + (long long)s * mstride + (long long)zf * Nc * Nc;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        const int gy = gy0 + a;
+        if (gy > 0 && gy < Nc - 1) dst[(long long)gy * Nc + gx] = yv[a];
+    }
+}
+
+// coarse[s][zc] = R_z mid[s]; grid (ceil(Nc^2 / 256), Nc, nstage)
+template <int K, typename T>
+__global__ void __launch_bounds__(256) restrict_z_kernel(const T* __restrict__ mid, T* __restrict__ coarse, int nc,
+                                                         long long mstride, long long cstride) {
+    const int Nc = nc * K + 1;
+    const long long NN = (long long)Nc * Nc;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NN) return;
+    const int zc = blockIdx.y, s = blockIdx.z;
+    T* dst = coarse + (long long)s * cstride + (long long)zc * NN + i;
+    const int yc = (int)(i / Nc), xc = (int)(i - (long long)yc * Nc);
+    if (zc == 0 || zc == Nc - 1 || xc == 0 || xc == Nc - 1 || yc == 0 || yc == Nc - 1) {
+        *dst = T(0);
+        return;
+    }
+    const int E = zc / K, a = zc - E * K;
+    const T* m = mid + (long long)s * mstride + i;
+    T v = T(0);
+    if (a == 0) {
+        // cell E-1 (t = 0..2k-1) and cell E (t = 0..2k)
+        const T* m0 = m + (long long)(2 * (E - 1) * K) * NN;
+        tfor<2 * K>([&](auto tm) {
+            constexpr int t = decltype(tm)::value;
+            if constexpr (PE<K, t, K>::v != 0.0) v = fma(T(PE<K, t, K>::v), m0[t * NN], v);
+        });
+        const T* m1 = m + (long long)(2 * E * K) * NN;
+        tfor<2 * K + 1>([&](auto tm) {
+            constexpr int t = decltype(tm)::value;
+            if constexpr (PE<K, t, 0>::v != 0.0) v = fma(T(PE<K, t, 0>::v), m1[t * NN], v);
+        });
+    } else {
+        const T* m1 = m + (long long)(2 * E * K) * NN;
+        tfor<K - 1>([&](auto am) {
+            constexpr int aa = decltype(am)::value + 1;
+            if (a == aa) {
+                tfor<2 * K + 1>([&](auto tm) {
+                    constexpr int t = decltype(tm)::value;
+                    if constexpr (PE<K, t, aa>::v != 0.0) v = fma(T(PE<K, t, aa>::v), m1[t * NN], v);
+                });
+            }
+        });
+    }
+    *dst = v;
+}
+
+template <int K, typename T>
+hipError_t restrict_typed(const void* fine, void* coarse, void* tmp, int nc, int nstage, long long fstride,
+                          long long cstride, hipStream_t st) {
+    using TL = RTile<K>;
+    const int Nc = nc * K + 1, Nf = 2 * nc * K + 1;
+    const long long mstride = (long long)Nf * Nc * Nc;
+    // tiles cover coarse nodes 0 .. Nc-2 (node Nc-1 is boundary)
+    const int tiles_x = (Nc - 1 + TL::TX - 1) / TL::TX, tiles_y = (Nc - 1 + TL::TY - 1) / TL::TY;
+    restrict_xy_kernel<K, T><<<dim3(tiles_x * tiles_y, Nf, nstage), TL::NT, 0, st>>>(
+        static_cast<const T*>(fine), static_cast<T*>(tmp), nc, tiles_x, fstride, mstride);
+    const long long NN = (long long)Nc * Nc;
+    restrict_z_kernel<K, T><<<dim3((unsigned)((NN + 255) / 256), Nc, nstage), 256, 0, st>>>(
+        static_cast<const T*>(tmp), static_cast<T*>(coarse), nc, mstride, cstride);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t restrict_k(int dtype, const void* fine, void* coarse, void* tmp, int nc, int nstage,
+                      long long fstride, long long cstride, hipStream_t st) {
+    return dtype == RK_FP64 ? restrict_typed<K, double>(fine, coarse, tmp, nc, nstage, fstride, cstride, st)
+                            : restrict_typed<K, float>(fine, coarse, tmp, nc, nstage, fstride, cstride, st);
+}
+
 template <int K, typename T>
 hipError_t prolong_typed(const void* coarse, void* fine, int nc, int nstage, long long cstride,
                          long long fstride, hipStream_t st) {
@@ -200,7 +375,9 @@ hipError_t prolong_typed(const void* coarse, void* fine, int nc, int nstage, lon
     p.fstride = fstride;
     p.nc = nc;
     const int Nf = 2 * nc * K + 1;
-    p.tiles = (Nf + TL::TF - 1) / TL::TF;
+    // tiles cover fine nodes 0 .. Nf-2: node Nf-1 is boundary, where the
+    // correction is zero
+    p.tiles = (Nf - 1 + TL::TF - 1) / TL::TF;
     // coarse cells per z-chunk: enough workgroups to fill the chip
     int czc = 8;
     while (czc > 1 && (long long)p.tiles * p.tiles * ((nc + czc - 1) / czc) * nstage < 2048) czc /= 2;
@@ -220,6 +397,19 @@ hipError_t prolong_k(int dtype, const void* coarse, void* fine, int nc, int nsta
 }
 
 }  // namespace
+
+hipError_t launch_restrict(int k, int dtype, const void* fine, void* coarse, void* tmp, int nc, int nstage,
+                           long long fstride, long long cstride, hipStream_t st) {
+    switch (k) {
+        case 1: return restrict_k<1>(dtype, fine, coarse, tmp, nc, nstage, fstride, cstride, st);
+        case 2: return restrict_k<2>(dtype, fine, coarse, tmp, nc, nstage, fstride, cstride, st);
+        case 3: return restrict_k<3>(dtype, fine, coarse, tmp, nc, nstage, fstride, cstride, st);
+        case 4: return restrict_k<4>(dtype, fine, coarse, tmp, nc, nstage, fstride, cstride, st);
+        case 5: return restrict_k<5>(dtype, fine, coarse, tmp, nc, nstage, fstride, cstride, st);
+        case 6: return restrict_k<6>(dtype, fine, coarse, tmp, nc, nstage, fstride, cstride, st);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_prolong_add(int k, int dtype, const void* coarse, void* fine, int nc, int nstage,
                               long long cstride, long long fstride, hipStream_t st) {
