@@ -17,8 +17,15 @@ Reported:
   (84 flop per stage-DoF for Q_4 against the 78.6 TFLOP/s non-packed fp32
   rate), with the HBM view (8 B per stage-DoF against 8 TB/s) beside it and
   the HBM bytes that the FETCH_SIZE / WRITE_SIZE counters measured;
-* cpu_baseline: the oracle's assembled block operator (scipy CSR SpMV) on a
-  bounded sample (16^3 cells, Q_4, same Q and tau), in the same unit.
+* plain_fp64_per_stage: the same steps with the preconditioner in fp64 and
+  the Q blocks solved one after another (the unbatched, full-precision form);
+* host leg (skipped with --no-cpu), the only part that runs the oracle:
+  cpu_baseline, the oracle's assembled block operator (scipy CSR SpMV) on a
+  bounded sample (16^3 cells, Q_4, same Q and tau), in the same unit; and
+  accuracy_vs_oracle, the error of one GPU step on the 32^3 Q_4 grid against
+  the oracle's exact step for FGMRES tolerances 1e-6 .. 1e-10.  The loosest
+  tolerance within 1e-8 then sets at_1e-8_accuracy: s per step of both forms
+  at that accuracy.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        python bench.py --mode op [--op-reps R]      (operator launches + one
@@ -139,11 +146,43 @@ def time_op(torch, R, ctx, form, u, v, reps):
     return t0.elapsed_time(t1) * 1e-3 / reps
 
 
-def cpu_baseline(n=16, k=4, Q=4, tau=5e-4, budget_s=12.0):
-    """Oracle block operator v_i = (lam_i M + tau K) u_i by assembled CSR SpMV."""
+RTOLS = (1e-6, 1e-7, 1e-8, 1e-9, 1e-10)
+
+
+def time_steps(torch, R, n, k, Q, tau, steps, warmup, y0, **opts):
+    """Average wall time of `steps` Radau IIA steps after `warmup` steps, from
+    the seeded initial data, synchronised on both sides; FGMRES iterations."""
+    s = R.RadauIIA(n, k, Q, tau, **opts)
+    y = y0.clone()
+    t = 0.0
+    for _ in range(warmup):
+        s.step(t, y)
+        t += tau
+    torch.cuda.synchronize()
+    its, vcs = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = s.step(t, y)
+        its.append(st["iterations"])
+        vcs.append(st["vcycles"])
+        t += tau
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    s.close()
+    return dt, its, vcs
+
+
+def cpu_baseline_leg(torch, R, n=16, k=4, Q=4, tau=5e-4, budget_s=12.0):
+    """The host-side leg, the only part of the bench that runs the oracle:
+    * the oracle's assembled block operator v_i = (lam_i M + tau K) u_i by CSR
+      SpMV (scipy, one thread) on a bounded sample, timed on the host cores;
+    * the oracle's exact (modal) Radau IIA step on the 32^3 Q_4 grid, the
+      reference for the error of GPU steps at several FGMRES tolerances."""
     import numpy as np
     from oracle.assemble import Problem
+    from oracle.step import ModalSolver
     from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
     p = Problem(n, k, "kron")
     tab = RadauIIA(Q)
     A = [(l * p.M + tau * p.K).tocsr() for l in tab.lam]
@@ -156,34 +195,39 @@ def cpu_baseline(n=16, k=4, Q=4, tau=5e-4, budget_s=12.0):
             A[i] @ u[i]
         reps += 1
         t = time.perf_counter() - t0
-    return {"value": Q * N ** 3 * reps / t, "unit": "stage-DoFs/s", "cores": 1, "kind": "oracle",
-            "sample": f"assembled block operator (lam_i M + tau K, scipy CSR SpMV, single thread) on "
-                      f"{n}^3 cells Q_{k} (N={N}), Q={Q}, {reps} applies in {t:.1f} s",
-            "host_cpu_count": os.cpu_count()}
-
-
-def accuracy_vs_oracle(torch, R):
-    """Error of the mixed-precision batched step against the exact oracle step
-    on the 32^3 Q_4 grid (Q = 4, tau = 5e-4, same seeded data)."""
-    import numpy as np
-    from oracle.step import ModalSolver
-    from oracle.tableau import RadauIIA
-    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
-    n, k, Q, tau = 32, 4, 4, 5e-4
-    s = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, rtol=1e-10)
-    x1 = grid_coords(s.info["nodes"], n)
-    y0 = fourier_field(x1, seed=0)
-    y = torch.tensor(y0, device="cuda")
-    st = s.step(0.0, y)
-    N = n * k + 1
-    inner = lambda v: v.reshape(N, N, N)[1:-1, 1:-1, 1:-1].reshape(-1)
-    t0 = time.perf_counter()
-    ref = ModalSolver(n, k).step(RadauIIA(Q), tau, inner(y0))
-    t_oracle = time.perf_counter() - t0
-    err = float(np.linalg.norm(inner(y.cpu().numpy()) - ref) / np.linalg.norm(ref))
+    cpu = {"value": Q * N ** 3 * reps / t, "unit": "stage-DoFs/s", "cores": 1, "kind": "oracle",
+           "sample": f"assembled block operator (lam_i M + tau K, scipy CSR SpMV, single thread) on "
+                     f"{n}^3 cells Q_{k} (N={N}), Q={Q}, {reps} applies in {t:.1f} s",
+           "host_cpu_count": os.cpu_count()}
+    # accuracy of GPU steps against the exact step, 32^3 Q_4, Q = 4, tau = 5e-4
+    na, Qa = 32, 4
+    Na = na * k + 1
+    inner = lambda v: v.reshape(Na, Na, Na)[1:-1, 1:-1, 1:-1].reshape(-1)
+    s = R.RadauIIA(na, k, Qa, tau)
+    x1 = grid_coords(s.info["nodes"], na)
     s.close()
-    return {"grid": "32^3 cells Q_4, Q=4, tau=5e-4, mixed batched, rtol 1e-10", "rel_l2_error": err,
-            "fgmres_iterations": st["iterations"], "oracle_modal_step_s": t_oracle}
+    y0 = fourier_field(x1, seed=0)
+    t0 = time.perf_counter()
+    ref = ModalSolver(na, k).step(RadauIIA(Qa), tau, inner(y0))
+    t_oracle = time.perf_counter() - t0
+    acc = {"grid": "32^3 cells Q_4, Q=4, tau=5e-4, same seeded data", "oracle_modal_step_s": t_oracle,
+           "mixed_batched": {}, "fp64_per_stage": {}}
+    for name, prec, mode in (("mixed_batched", R.RK_PREC_MIXED, R.RK_BATCHED),
+                             ("fp64_per_stage", R.RK_PREC_FP64, R.RK_PER_STAGE)):
+        for rtol in RTOLS:
+            s = R.RadauIIA(na, k, Qa, tau, precision=prec, mode=mode, rtol=rtol)
+            y = torch.tensor(y0, device="cuda")
+            st = s.step(0.0, y)
+            err = float(np.linalg.norm(inner(y.cpu().numpy()) - ref) / np.linalg.norm(ref))
+            acc[name][f"{rtol:.0e}"] = {"rel_l2_error": err, "fgmres_iterations": st["iterations"]}
+            s.close()
+    return cpu, acc
+
+
+def loosest_rtol(acc_runs, bound=1e-8):
+    """The loosest FGMRES tolerance whose step error is within `bound`."""
+    ok = [float(r) for r, v in acc_runs.items() if v["rel_l2_error"] <= bound]
+    return max(ok) if ok else min(RTOLS)
 
 
 def main():
@@ -254,31 +298,40 @@ def main():
     del u64, v64
     torch.cuda.empty_cache()
     sdofs = Q * N ** 3
-    # Radau IIA steps
     x1 = grid_coords(solver.info["nodes"], n)
-    y = torch.tensor(fourier_field(x1, seed=0), device="cuda")
-    t = 0.0
-    for _ in range(args.warmup):
-        solver.step(t, y)
-        t += tau
-    torch.cuda.synchronize()
-    its, vcs = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = solver.step(t, y)
-        its.append(st["iterations"])
-        vcs.append(st["vcycles"])
-        t += tau
-    torch.cuda.synchronize()
-    t_step = (time.perf_counter() - t0) / max(args.steps, 1)
+    y0 = torch.tensor(fourier_field(x1, seed=0), device="cuda")
+    opts = solver.opts
+    solver.close()
+    mixed = dict(precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, **smoother)
+    plain = dict(precision=R.RK_PREC_FP64, mode=R.RK_PER_STAGE, **smoother)
+    # Radau IIA steps at FGMRES rtol 1e-10
+    t_step, its, vcs = time_steps(torch, R, n, k, Q, tau, args.steps, args.warmup, y0, rtol=1e-10, **mixed)
     log(f"[bench] {t_step * 1e3:.2f} ms/step, FGMRES its {its}")
     # per-component breakdown of one extra step
-    solver.close()
-    solver = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, rtol=1e-10, timing=1,
-                        **smoother)
-    breakdown = solver.step(t, y)
-    solver.close()
+    s = R.RadauIIA(n, k, Q, tau, rtol=1e-10, timing=1, **mixed)
+    y = y0.clone()
+    breakdown = s.step(0.0, y)
+    s.close()
     del y
+    # the plain fp64 per-stage form on the same workload
+    ps = max(1, min(3, args.steps))
+    t_plain, its_plain, _ = time_steps(torch, R, n, k, Q, tau, ps, 1, y0, rtol=1e-10, **plain)
+    log(f"[bench] plain fp64 per-stage: {t_plain * 1e3:.2f} ms/step, its {its_plain}")
+    at_acc = None
+    cpu = acc = None
+    if not args.no_cpu:
+        log("[bench] host leg: cpu baseline and accuracy against the oracle on 32^3")
+        cpu, acc = cpu_baseline_leg(torch, R)
+        r_mixed = loosest_rtol(acc["mixed_batched"])
+        r_plain = loosest_rtol(acc["fp64_per_stage"])
+        tm, im, _ = time_steps(torch, R, n, k, Q, tau, args.steps, 1, y0, rtol=r_mixed, **mixed)
+        tp, ip, _ = time_steps(torch, R, n, k, Q, tau, ps, 1, y0, rtol=r_plain, **plain)
+        at_acc = {"bound": 1e-8, "mixed_batched": {"rtol": r_mixed, "ms_per_step": tm * 1e3, "fgmres_iterations": im},
+                  "fp64_per_stage": {"rtol": r_plain, "ms_per_step": tp * 1e3, "fgmres_iterations": ip},
+                  "speedup": tp / tm}
+        log(f"[bench] at 1e-8 accuracy: mixed batched {tm * 1e3:.2f} ms (rtol {r_mixed:.0e}), "
+            f"plain fp64 per-stage {tp * 1e3:.2f} ms (rtol {r_plain:.0e})")
+    del y0
     torch.cuda.empty_cache()
     flop = op_flops_per_stage_dof(k)
     achieved = flop * sdofs / t_blk / 1e12
@@ -300,10 +353,13 @@ def main():
                                f"mixed precision, batched stages",
                    "n_cells": n, "degree": k, "Q": Q, "tau": tau, "stage_dofs": sdofs,
                    "precision": "mixed", "mode": "batched", "rtol": 1e-10,
-                   "cheb_degree": solver.opts.cheb_degree, "cheb_range": solver.opts.cheb_range},
+                   "cheb_degree": opts.cheb_degree, "cheb_range": opts.cheb_range},
         "s_per_step": t_step,
         "fgmres_iterations_per_step": its,
         "vcycles_per_step": vcs,
+        "plain_fp64_per_stage": {"ms_per_step": t_plain * 1e3, "fgmres_iterations": its_plain, "rtol": 1e-10,
+                                 "speedup_of_mixed_batched": t_plain / t_step},
+        "at_1e-8_accuracy": at_acc,
         "step_breakdown_s": {k2: breakdown[k2] for k2 in ("t_rhs", "t_vmult", "t_basis", "t_blocks", "t_rest")},
         "operators": {
             "blocks_fp32_us": t_blk * 1e6,
@@ -320,10 +376,9 @@ def main():
                      "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": hbm_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": 8 * sdofs}},
     }
-    if not args.no_cpu:
-        log("[bench] accuracy vs oracle on 32^3 and cpu baseline")
-        out["accuracy_vs_oracle"] = accuracy_vs_oracle(torch, R)
-        out["cpu_baseline"] = cpu_baseline()
+    if cpu is not None:
+        out["accuracy_vs_oracle"] = acc
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 
