@@ -91,9 +91,12 @@ struct Tile {
     static constexpr int CY = 8;
     static constexpr int TY = CY * K;                       // owned nodes in y
     static constexpr int NT = TX * CY;                      // threads
-    static constexpr int RX = TX + K + 1;                   // staged input width
+    static constexpr int RW = TX + K + 1;                   // staged input width
+    // LDS pitches are 2 (mod 4): lanes of a 16-lane group then read
+    // adjacent pairs (ds_read2) from distinct banks
+    static constexpr int RX = RW + ((2 - RW % 4) + 4) % 4;  // staged row pitch
     static constexpr int RY = TY + K + 1;                   // staged input height
-    static constexpr int XP = TX + 1;                       // padded LDS row of X1/X2
+    static constexpr int XP = RY + ((2 - RY % 4) + 4) % 4;  // X1/X2 column pitch (stored x-major)
 };
 
 template <typename T>
@@ -107,8 +110,8 @@ struct OpArgs {
     int n, s0, nstage;
     int tiles_x, tiles_y, chunks_z, nwork, per_xcd;
     int cz;                                       // elements per z-chunk
-    int xo_zero;
-    T ca, cb, icb;                                // Chebyshev coefficients, icb = 1/cb
+    int xo_zero, xo_from_b;
+    T ca, cb, icb, c0;                            // Chebyshev coefficients, icb = 1/cb
     T alpha[RK_MAX_Q], beta[RK_MAX_Q];            // per-stage scales
 };
 
@@ -155,7 +158,7 @@ __device__ __forceinline__ T diag_rt(int r) {
 // 2k^2 + 3k extra values), otherwise the allocator's own choice.
 template <int K, typename T, int EPI>
 struct MinWaves {
-    static constexpr int v = (sizeof(T) == 4 && EPI == EPI_CHEB && K <= 4) ? 3 : 1;
+    static constexpr int v = (sizeof(T) == 4 && (EPI == EPI_CHEB || EPI == EPI_CHEB1) && K <= 4) ? 3 : 1;
 };
 
 template <int K, typename T, int MIX, int EPI>
@@ -165,10 +168,12 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
     constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, RX = TL::RX, RY = TL::RY;
     constexpr int XP = TL::XP, CX = TL::CX;
     constexpr int NU = MIX == MIX_PAIR ? 2 : 1;
+    constexpr bool CHEB = EPI == EPI_CHEB || EPI == EPI_CHEB1;
+    constexpr bool INB = EPI == EPI_CHEB1;               // input x1 = c0 D^-1 b, formed from b
     constexpr int NBUF = sizeof(T) == 4 ? 2 : 1;          // LDS buffers per array
     constexpr int NSLOT = (RY * RX + NT - 1) / NT;      // staged values per thread
     constexpr int NXIT = (RY * CX + NT - 1) / NT;       // x-pass items per thread
-    constexpr int USZ = NU * RY * RX, XSZ = RY * XP;
+    constexpr int USZ = NU * RY * RX, XSZ = TX * XP;
     __shared__ T sU[NBUF * USZ];
     __shared__ T sX1[NBUF * XSZ];
     __shared__ T sX2[NBUF * XSZ];
@@ -219,6 +224,13 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
     const T* __restrict__ us = p.u + (long long)s * p.stride;
     const T* __restrict__ us2 = MIX == MIX_PAIR ? p.u2 + (long long)s * p.stride : nullptr;
 
+    // 1 / D for the Chebyshev steps (fp32: hardware reciprocal; the
+    // smoother is a preconditioner, so the last-bit rounding is immaterial)
+    auto recip = [](T d) __attribute__((always_inline)) {
+        if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(d);
+        else return T(1) / d;
+    };
+
     // Load slots of this thread: in-plane byte offset and validity (interior in x, y).
     unsigned soff[NSLOT];
     unsigned smask = 0;
@@ -227,15 +239,37 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
         const int i = tid + m * NT;
         const int r = i / RX, c = i - r * RX;
         const int xx = X0 - K + c, yy = Y0 - K + r;
-        const bool ok = i < RY * RX && xx > 0 && xx < nK && yy > 0 && yy < nK;
+        const bool ok = i < RY * RX && c < TL::RW && xx > 0 && xx < nK && yy > 0 && yy < nK;
         soff[m] = ok ? ((unsigned)yy * (unsigned)N + (unsigned)xx) * (unsigned)sizeof(T) : 0u;
         smask |= ok ? (1u << m) : 0u;
     }
     T pre[NU][NSLOT];
+    // Fused first Chebyshev step: the staged input is x1 = c0 D^-1 b.  Per
+    // slot D = pa dMz + pb dKz with pa, pb from the slot's x and y position
+    // and dMz, dKz (1D diagonals at the plane's z) held for the issued plane.
+    T pa[INB ? NSLOT : 1], pb[INB ? NSLOT : 1];
+    T izm = T(1), izk = T(0);
+    if constexpr (INB) {
+#pragma unroll
+        for (int m = 0; m < NSLOT; ++m) {
+            const int i = tid + m * NT;
+            const int r = i / RX, c = i - r * RX;
+            const int rx = (X0 + c) % K, ry = (Y0 + r) % K;   // (X0 - K + c) mod K, X0 a multiple of K
+            const T mx = diag_rt<K, 0, T>(rx), kx = diag_rt<K, 1, T>(rx);
+            const T my = diag_rt<K, 0, T>(ry), ky = diag_rt<K, 1, T>(ry);
+            const bool ok = smask >> m & 1u;
+            pa[m] = ok ? fma(alpha, mx * my, beta * fma(kx, my, mx * ky)) : T(1);
+            pb[m] = ok ? beta * mx * my : T(0);
+        }
+    }
     // Issue the loads of plane z into registers (zeros outside the interior).
     // Every slot loads from a valid address (offset 0 for slots outside the
     // interior) and selects zero afterwards.
     auto issue = [&](int z) __attribute__((always_inline)) {
+        if constexpr (INB) {
+            izm = diag_rt<K, 0, T>(z % K);
+            izk = diag_rt<K, 1, T>(z % K);
+        }
         if (z > 0 && z < nK) {
             const char* __restrict__ pl = reinterpret_cast<const char*>(us + z * NN);
 #pragma unroll
@@ -264,7 +298,8 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
         for (int m = 0; m < NSLOT; ++m) {
             const int i = tid + m * NT;
             if (m < NSLOT - 1 || i < RY * RX) {
-                dst[i] = pre[0][m];
+                if constexpr (INB) dst[i] = pre[0][m] * (p.c0 * recip(fma(pa[m], izm, pb[m] * izk)));
+                else dst[i] = pre[0][m];
                 if (MIX == MIX_PAIR) dst[RY * RX + i] = pre[NU - 1][m];
             }
         }
@@ -287,15 +322,15 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
                 const T* src = &U[r * RX + cx * K];
 #pragma unroll
                 for (int j = 0; j <= 2 * K; ++j) wv[j] = src[j];
-                T* o1 = &X1[r * XP + cx * K];
-                T* o2 = &X2[r * XP + cx * K];
+                T* o1 = &X1[cx * K * XP + r];
+                T* o2 = &X2[cx * K * XP + r];
                 if (MIX == MIX_DIAG) {
                     row_apply<K, 0, T>(wv, mx);
                     row_apply<K, 1, T>(wv, kx);
 #pragma unroll
                     for (int a = 0; a < K; ++a) {
-                        o1[a] = fma(alpha, mx[a], beta * kx[a]);
-                        o2[a] = beta * mx[a];
+                        o1[a * XP] = fma(alpha, mx[a], beta * kx[a]);
+                        o2[a * XP] = beta * mx[a];
                     }
                 } else {
                     T wk[2 * K + 1], mk[K];
@@ -307,8 +342,8 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
                     row_apply<K, 0, T>(wk, mk);
 #pragma unroll
                     for (int a = 0; a < K; ++a) {
-                        o1[a] = fma(alpha, mx[a], beta * kx[a]);
-                        o2[a] = beta * mk[a];
+                        o1[a * XP] = fma(alpha, mx[a], beta * kx[a]);
+                        o2[a * XP] = beta * mk[a];
                     }
                 }
             }
@@ -321,8 +356,8 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
         T w1[2 * K + 1], w2[2 * K + 1], m1[K], k2[K];
 #pragma unroll
         for (int j = 0; j <= 2 * K; ++j) {
-            w1[j] = X1[(py * K + j) * XP + tx];
-            w2[j] = X2[(py * K + j) * XP + tx];
+            w1[j] = X1[tx * XP + py * K + j];
+            w2[j] = X2[tx * XP + py * K + j];
         }
         row_apply<K, 0, T>(w1, m1);
         row_apply<K, 1, T>(w2, k2);
@@ -355,20 +390,14 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
     const bool colok = gx < N;
     const bool xbnd = gx == 0 || gx == nK;
     T dmx = T(0), dkx = T(0);
-    if (EPI == EPI_CHEB) {
+    if (CHEB) {
         const int rx = gx % K;
         dmx = diag_rt<K, 0, T>(rx);
         dkx = diag_rt<K, 1, T>(rx);
     }
     const T* __restrict__ bs = (EPI != EPI_STORE) ? p.b + (long long)s * p.stride : nullptr;
-    const T* xos = (EPI == EPI_CHEB && !p.xo_zero) ? p.xo + (long long)s * p.stride : nullptr;
+    const T* xos = (CHEB && !p.xo_zero && !p.xo_from_b) ? p.xo + (long long)s * p.stride : nullptr;
 
-    // 1 / D for the Chebyshev epilogue (fp32: hardware reciprocal; the
-    // smoother is a preconditioner, so the last-bit rounding is immaterial)
-    auto recip = [](T d) __attribute__((always_inline)) {
-        if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(d);
-        else return T(1) / d;
-    };
     // Jacobi diagonal of the block operator at node (c, a) of the pencil:
     //   D = alpha dMx dMy dMz + beta (dKx dMy dMz + dMx dKy dMz + dMx dMy dKz)
     //     = C1 (alpha dMx + beta dKx) + C2 beta dMx,
@@ -387,6 +416,14 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
     const int E1 = min(E0 + CZ, n);                    // chunk elements E0 .. E1-1
     // Pencils whose nodes are all interior in x and y take the branch-free path.
     const bool pencil_inner = colok && !xbnd && gy0 > 0 && gy0 + K - 1 < nK;
+    // Chebyshev update x + ca (x - x_prev) + cb D^-1 (b - A x) at one node
+    // (rD = 1/D); x = c0 D^-1 b for the fused first step, x_prev = c0 D^-1 b
+    // when the previous iterate is the first one.
+    auto cheb_update = [&](T b, T x, T xo, T av, T rD) __attribute__((always_inline)) {
+        if (INB) x = p.c0 * b * rD;
+        if (!INB && p.xo_from_b) xo = p.c0 * b * rD;
+        return x + p.ca * (x - xo) + p.cb * (b - av) * rD;
+    };
     // Entry of a vector at this thread's column in the row that starts at
     // element offset ro (uniform 64-bit row base + 32-bit lane byte offset).
     auto at = [&](const T* base, long long ro) __attribute__((always_inline)) -> const T& {
@@ -407,6 +444,8 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
 #pragma unroll
     for (int a = 0; a < K; ++a) { fb[a] = T(0); fx[a] = T(0); fo[a] = T(0); }
     const T pu1 = ju1 * p.icb, pu2 = ju2 * p.icb;       // D / cb factors
+    // x_prev = c0 D^-1 b:  epre = b (1 - ca c0 / cb) + (1 + ca) x D / cb
+    const T opc = T(1) + p.ca, k1 = T(1) - p.ca * p.c0 * p.icb;
     // fetch the epilogue inputs of output plane c of element ee, whose input
     // plane is staged in sU[buf] (fast-path lanes of flushed elements only)
     auto pf_issue = [&](int ee, int c, int buf) __attribute__((always_inline)) {
@@ -417,7 +456,7 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
                 constexpr int a = decltype(am)::value;
                 const long long ro = zo + (long long)a * N;
                 fb[a] = at(bs, ro);
-                if (EPI == EPI_CHEB) {
+                if (CHEB) {
                     fx[a] = U[a * RX];
                     fo[a] = xos ? at(xos, ro) : T(0);
                 }
@@ -431,6 +470,8 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
             cfor<K>([&](auto am) {
                 constexpr int a = decltype(am)::value;
                 if (EPI == EPI_RESID) epre[c][a] = fb[a];
+                else if (p.xo_from_b)   // x_prev = c0 D^-1 b
+                    epre[c][a] = fma(fx[a] * opc, jac_s(cm, am, pu1, pu2), fb[a] * k1);
                 else epre[c][a] = fma(fma(p.ca, fx[a] - fo[a], fx[a]), jac_s(cm, am, pu1, pu2), fb[a]);
             });
         }
@@ -463,8 +504,8 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
                         constexpr int a = decltype(am)::value;
                         const long long ro = zo + (long long)a * N;
                         lb[a] = at(bs, ro);
-                        if (EPI == EPI_CHEB) {
-                            lx[a] = at(us, ro);
+                        if (CHEB) {
+                            lx[a] = INB ? T(0) : at(us, ro);
                             lo[a] = xos ? at(xos, ro) : T(0);
                         }
                     });
@@ -476,7 +517,7 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
                     T out;
                     if (EPI == EPI_STORE) out = av;
                     else if (EPI == EPI_RESID) out = lb[a] - av;
-                    else out = lx[a] + p.ca * (lx[a] - lo[a]) + p.cb * (lb[a] - av) * recip(jac(cm, am));
+                    else out = cheb_update(lb[a], lx[a], lo[a], av, recip(jac(cm, am)));
                     *reinterpret_cast<T*>(reinterpret_cast<char*>(vs + ro) + colbyte) = out;
                 });
             });
@@ -500,9 +541,9 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
                         if (EPI == EPI_STORE) out = av;
                         else if (EPI == EPI_RESID) out = bs[g] - av;
                         else {
-                            const T x = us[g];
+                            const T x = INB ? T(0) : us[g];
                             const T xo = xos ? xos[g] : T(0);
-                            out = x + p.ca * (x - xo) + p.cb * (bs[g] - av) * recip(jac(cm, am));
+                            out = cheb_update(bs[g], x, xo, av, recip(jac(cm, am)));
                         }
                     }
                     (vs + zo)[off] = out;
@@ -678,6 +719,8 @@ hipError_t launch_op_typed(const OpLaunch& L) {
     p.ca = T(L.ca);
     p.cb = T(L.cb);
     p.icb = L.cb != 0.0 ? T(1.0 / L.cb) : T(0);
+    p.c0 = T(L.c0);
+    p.xo_from_b = L.xo_from_b;
     for (int i = 0; i < RK_MAX_Q; ++i) {
         p.alpha[i] = T(L.alpha[i]);
         p.beta[i] = T(L.beta[i]);
@@ -691,6 +734,7 @@ hipError_t launch_op_typed(const OpLaunch& L) {
     RK_OP_CASE(MIX_DIAG, EPI_STORE)
     RK_OP_CASE(MIX_DIAG, EPI_RESID)
     RK_OP_CASE(MIX_DIAG, EPI_CHEB)
+    RK_OP_CASE(MIX_DIAG, EPI_CHEB1)
     RK_OP_CASE(MIX_PAIR, EPI_STORE)
     RK_OP_CASE(MIX_PAIR, EPI_RESID)
 #undef RK_OP_CASE

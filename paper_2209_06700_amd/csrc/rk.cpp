@@ -287,8 +287,9 @@ struct Timer {
 // u2 the stiffness-term input.
 int op(rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, void* v,
        const void* b, const void* xo, int n, int s0, int ns, double ca, double cb,
-       const void* u2 = nullptr) {
+       const void* u2 = nullptr, int xo_from_b = 0, double c0 = 0.0) {
     OpLaunch L;
+    L.xo_from_b = xo_from_b; L.c0 = c0;
     L.k = k; L.dtype = dtype; L.mix = cf.pair ? MIX_PAIR : MIX_DIAG; L.epi = epi;
     L.u = u; L.u2 = u2; L.v = v; L.b = b; L.xo = xo;
     for (int i = 0; i < RK_MAX_Q; ++i) { L.alpha[i] = cf.alpha[i]; L.beta[i] = cf.beta[i]; }
@@ -322,27 +323,42 @@ int chebyshev(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, void
     Level& L = c->lv[l];
     const ChebCoef cc = cheb_coef(L.eig_max, c->opt.cheb_range);
     const int k = c->k, dt = c->pc;
-    void* cur;     // x_j
-    void* prev;    // x_{j-1} (or null when x_{j-1} = 0)
-    void* other;
-    if (zero_start) {
-        HIPCHK(c, launch_cheb_first(k, dt, to_stage_scal(L.blk), b, first, L.n, s0, ns, 1.0 / cc.theta, c->stream));
-        cur = first; prev = nullptr; other = second;
-    } else {
-        int rc = op(c, k, dt, EPI_CHEB, L.blk, first, second, b, nullptr, L.n, s0, ns, 0.0, 1.0 / cc.theta);
-        if (rc) return rc;
-        cur = second; prev = first; other = first;
+    const double c0 = 1.0 / cc.theta;          // x_1 = c0 D^-1 b from a zero start
+    if (zero_start && degree == 1) {
+        HIPCHK(c, launch_cheb_first(k, dt, to_stage_scal(L.blk), b, first, L.n, s0, ns, c0, c->stream));
+        *res = first;
+        return RK_OK;
     }
+    void* cur;            // x_j
+    void* prev;           // buffer of x_{j-1} (null: x_{j-1} = 0)
+    bool prev_x1 = false; // x_{j-1} = x_1 = c0 D^-1 b, formed from b instead of stored
     double rho = 1.0 / cc.sigma;
-    for (int j = 1; j < degree; ++j) {
+    int j = 1;
+    if (zero_start) {
+        // x_2 straight from b: the kernel forms x_1 while it stages b
         const double rho_new = 1.0 / (2.0 * cc.sigma - rho);
         const double ca = rho_new * rho, cb = 2.0 * rho_new / cc.delta;
-        // x_{j+1} overwrites the buffer of x_{j-1} (or the free buffer)
-        void* out = prev ? prev : other;
-        int rc = op(c, k, dt, EPI_CHEB, L.blk, cur, out, b, prev, L.n, s0, ns, ca, cb);
+        int rc = op(c, k, dt, EPI_CHEB1, L.blk, b, second, b, nullptr, L.n, s0, ns, ca, cb, nullptr, 0, c0);
+        if (rc) return rc;
+        cur = second; prev = first; prev_x1 = true;
+        rho = rho_new;
+        j = 2;
+    } else {
+        int rc = op(c, k, dt, EPI_CHEB, L.blk, first, second, b, nullptr, L.n, s0, ns, 0.0, c0);
+        if (rc) return rc;
+        cur = second; prev = first;
+    }
+    for (; j < degree; ++j) {
+        const double rho_new = 1.0 / (2.0 * cc.sigma - rho);
+        const double ca = rho_new * rho, cb = 2.0 * rho_new / cc.delta;
+        // x_{j+1} overwrites the buffer of x_{j-1}
+        void* out = prev;
+        int rc = op(c, k, dt, EPI_CHEB, L.blk, cur, out, b, prev_x1 ? nullptr : prev, L.n, s0, ns, ca, cb,
+                    nullptr, prev_x1 ? 1 : 0, c0);
         if (rc) return rc;
         prev = cur;
         cur = out;
+        prev_x1 = false;
         rho = rho_new;
     }
     *res = cur;

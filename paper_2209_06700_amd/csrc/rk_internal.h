@@ -52,7 +52,10 @@ struct StageScal {
 // Kernel launchers (implemented in the .hip units).  All return hipError_t.
 // ---------------------------------------------------------------------------
 enum Mix { MIX_DIAG = 0, MIX_PAIR = 1 };
-enum Epi { EPI_STORE = 0, EPI_RESID = 1, EPI_CHEB = 2 };
+// Epilogues of the operator kernel.  EPI_CHEB1 is EPI_CHEB whose input is
+// the first Chebyshev iterate x1 = c0 D^-1 b formed from b while it is staged
+// (u = b, x_prev = 0), so x1 is never stored.
+enum Epi { EPI_STORE = 0, EPI_RESID = 1, EPI_CHEB = 2, EPI_CHEB1 = 3 };
 
 struct OpLaunch {
     int k = 0;
@@ -70,6 +73,10 @@ struct OpLaunch {
     int n = 0;                 // cells per direction
     int s0 = 0, nstage = 1;    // stages [s0, s0 + nstage)
     double ca = 0.0, cb = 0.0; // EPI_CHEB: x_new = x + ca (x - xo) + cb D^-1 (b - A x)
+    // EPI_CHEB with xo_from_b: x_prev = c0 D^-1 b (the first iterate, formed
+    // from b instead of read); EPI_CHEB1: the input is c0 D^-1 b
+    int xo_from_b = 0;
+    double c0 = 0.0;
     hipStream_t stream = nullptr;
 };
 hipError_t launch_op(const OpLaunch& L);
