@@ -99,6 +99,12 @@ struct rk_ctx {
     Tableau tab{};
     Element1D el{};
     hipStream_t stream = nullptr;
+    // The fine-level V-cycle (F.b -> F.x, fixed buffers) is captured once into
+    // a HIP graph on a private stream and replayed on `stream`: the coarse
+    // levels are tens of small launches whose dispatch cost the graph cuts.
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t vc_exec = nullptr;
+    int vc_graph = 0;              // 0 not tried, 1 captured, -1 eager only
     int pc = RK_FP64;              // preconditioner dtype
     std::vector<Level> lv;
     Coeffs form[F_NFORMS];         // fine-level operator coefficients
@@ -430,6 +436,41 @@ int vcycle_all(rk_ctx* c, const void* b, void* x) {
     return RK_OK;
 }
 
+// V-cycles F.b -> F.x for all blocks: replay of the captured graph, or eager
+// launches (timing mode, RK_NO_GRAPH set, or capture unavailable).
+int run_vcycle(rk_ctx* c) {
+    Level& F = c->lv[0];
+    static const bool no_graph = std::getenv("RK_NO_GRAPH") != nullptr;   // A/B override
+    if (c->opt.timing || no_graph || c->vc_graph < 0) return vcycle_all(c, F.b, F.x);
+    if (c->vc_graph == 0) {
+        c->vc_graph = -1;
+        if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return vcycle_all(c, F.b, F.x);
+        }
+        if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return vcycle_all(c, F.b, F.x);
+        }
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        const int rc = vcycle_all(c, F.b, F.x);
+        c->stream = user;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (rc == RK_OK && e == hipSuccess && g) e = hipGraphInstantiate(&c->vc_exec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != RK_OK || e != hipSuccess || !c->vc_exec) {
+            (void)hipGetLastError();
+            c->vc_exec = nullptr;
+            return vcycle_all(c, F.b, F.x);
+        }
+        c->vc_graph = 1;
+    }
+    HIPCHK(c, hipGraphLaunch(c->vc_exec, c->stream));
+    return RK_OK;
+}
+
 // z = P^-1 r (eq. irk:P); r, z fp64 [Q][N3].  If m is given, m = (A^-1 (x) I) z
 // is written in the same pass (the mass-term input of the operator of eq. irk:A).
 int precondition(rk_ctx* c, const double* r, double* z, double* m = nullptr,
@@ -442,7 +483,7 @@ int precondition(rk_ctx* c, const double* r, double* z, double* m = nullptr,
     }
     {
         Timer t(c, C_BLOCKS);
-        int rc = vcycle_all(c, F.b, F.x);
+        int rc = run_vcycle(c);
         if (rc) return rc;
     }
     Timer t(c, C_BASIS);
@@ -624,6 +665,8 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
 int rk_destroy(rk_ctx* c) {
     if (!c) return RK_EINVAL;
     for (auto& e : c->event_pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    if (c->vc_exec) (void)hipGraphExecDestroy(c->vc_exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return RK_OK;
 }

@@ -153,3 +153,26 @@ def test_full_size_32cubed_q4_per_stage_fp64(R):
         print(f"32^3 step {s}: its={stats['iterations']} err={err:.3e}", flush=True)
         assert err <= 1e-10
     solver.close()
+
+
+@pytest.mark.parametrize("Q,prec,bar", [(3, "fp64", 1e-10), (5, "fp64", 1e-10), (4, "mixed", 1e-8)])
+def test_full_size_32cubed_q4_batched(R, Q, prec, bar):
+    """32^3 cells, Q_4, all Q stages batched (Q = 3, 5 in fp64; Q = 4 mixed),
+    tau = 1e-3, rtol 1e-10: one step of the seeded Fourier data against the
+    modal oracle."""
+    from oracle.step import ModalSolver
+    from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
+    n, k, tau = 32, 4, 1e-3
+    print(f"32^3 batched Q={Q} {prec}", flush=True)
+    solver = R.RadauIIA(n, k, Q, tau, mode=R.RK_BATCHED, precision=PREC[prec][0], rtol=1e-10)
+    y0 = fourier_field(grid_coords(solver.info["nodes"], n), seed=0)
+    y = torch.tensor(y0, device="cuda")
+    N = n * k + 1
+    inner = lambda v: v.reshape(N, N, N)[1:-1, 1:-1, 1:-1].reshape(-1)
+    stats = solver.step(0.0, y)
+    ref = ModalSolver(n, k).step(RadauIIA(Q), tau, inner(y0))
+    err = _rel(inner(y.cpu().numpy()), ref)
+    print(f"32^3 batched Q={Q} {prec}: its={stats['iterations']} err={err:.3e}", flush=True)
+    assert err <= bar
+    solver.close()
