@@ -431,15 +431,14 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
     };
     // Epilogue prefetch (fp32 march, residual and Chebyshev epilogues): the
     // epilogue inputs of output plane c of an element are fetched in the
-    // iteration that x-passes that plane and folded into epre[c] in the next
-    // one, so epre is complete when the element is written and the writes
+    // iteration that x-passes that plane and, in the next one, subtracted
+    // from the accumulator of that output (acc = A x - epre), so the writes
     // wait on no load.  x itself comes from the staged plane in LDS (no second
     // read from memory).  For the Chebyshev update
     //   out = x + ca (x - x_prev) + cb D^-1 (b - A x) = (cb / D) (epre - A x),
     //   epre = b + (x + ca (x - x_prev)) D / cb;
     // for the residual epre = b.
     constexpr bool PF = EPI != EPI_STORE && NBUF == 2 && K <= 4;   // registers allow it up to Q_4
-    T epre[PF ? K : 1][K];
     T fb[K], fx[K], fo[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) { fb[a] = T(0); fx[a] = T(0); fo[a] = T(0); }
@@ -463,16 +462,18 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
             });
         }
     };
-    // fold the inputs fetched for output plane c into epre[c]
+    // fold the inputs fetched for output plane c into its accumulators
     auto pf_fold = [&](auto cm) __attribute__((always_inline)) {
         constexpr int c = decltype(cm)::value;
         if constexpr (PF) {
             cfor<K>([&](auto am) {
                 constexpr int a = decltype(am)::value;
-                if (EPI == EPI_RESID) epre[c][a] = fb[a];
+                T e;
+                if (EPI == EPI_RESID) e = fb[a];
                 else if (p.xo_from_b)   // x_prev = c0 D^-1 b
-                    epre[c][a] = fma(fx[a] * opc, jac_s(cm, am, pu1, pu2), fb[a] * k1);
-                else epre[c][a] = fma(fma(p.ca, fx[a] - fo[a], fx[a]), jac_s(cm, am, pu1, pu2), fb[a]);
+                    e = fma(fx[a] * opc, jac_s(cm, am, pu1, pu2), fb[a] * k1);
+                else e = fma(fma(p.ca, fx[a] - fo[a], fx[a]), jac_s(cm, am, pu1, pu2), fb[a]);
+                acc[c][a] -= e;
             });
         }
     };
@@ -487,7 +488,7 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
                 cfor<K>([&](auto am) {
                     constexpr int a = decltype(am)::value;
                     const long long ro = zo + (long long)a * N;
-                    const T d = epre[PF ? c : 0][a] - acc[c][a];
+                    const T d = -acc[c][a];                      // epre - A x
                     const T out = EPI == EPI_RESID ? d : p.cb * recip(jac(cm, am)) * d;
                     *reinterpret_cast<T*>(reinterpret_cast<char*>(vs + ro) + colbyte) = out;
                 });
