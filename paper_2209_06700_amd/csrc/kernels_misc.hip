@@ -347,13 +347,6 @@ __global__ void reduce_kernel(const double* __restrict__ part, int nblocks, int 
     }
 }
 
-__global__ void __launch_bounds__(kBlock) normalize_kernel(double* __restrict__ v, const double* __restrict__ w,
-                                                           const double* __restrict__ nrm2, long long n) {
-    const double inv = 1.0 / sqrt(*nrm2);
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        v[i] = w[i] * inv;
-}
 
 // kv += sum_u y[u] Z_u for a chunk of NV vectors (Z fp64 or fp32)
 template <int NV, typename TZ, bool V2>
@@ -604,10 +597,6 @@ hipError_t launch_reduce(const double* part, int nblocks, int nout, double* out,
     return hipGetLastError();
 }
 
-hipError_t launch_normalize(double* v, const double* w, const double* nrm2, long long n, hipStream_t st) {
-    normalize_kernel<<<grid_for(n), kBlock, 0, st>>>(v, w, nrm2, n);
-    return hipGetLastError();
-}
 
 hipError_t launch_combine(double* kv, int dtype_z, const void* Z, int nz, long long ld, const double* y,
                           long long n, hipStream_t st) {

@@ -153,12 +153,15 @@ __device__ __forceinline__ T diag_rt(int r) {
     return d;
 }
 
-// Minimum waves per SIMD requested from the register allocator: three for
-// the fp32 Chebyshev kernel of degree <= 4 (its epilogue prefetch holds
-// 2k^2 + 3k extra values), otherwise the allocator's own choice.
+// Minimum waves per SIMD requested from the register allocator for the fp32
+// Chebyshev kernels of degree <= 4, which hold the epilogue prefetch (3k
+// values) on top of the operator's registers: four for the general step
+// (measured 13% faster than three), three for the fused first step (which
+// also holds the staging scales and spills at four).  Otherwise the
+// allocator's own choice.
 template <int K, typename T, int EPI>
 struct MinWaves {
-    static constexpr int v = (sizeof(T) == 4 && (EPI == EPI_CHEB || EPI == EPI_CHEB1) && K <= 4) ? 3 : 1;
+    static constexpr int v = (sizeof(T) != 4 || K > 4) ? 1 : EPI == EPI_CHEB ? 4 : EPI == EPI_CHEB1 ? 3 : 1;
 };
 
 template <int K, typename T, int MIX, int EPI>
@@ -442,22 +445,23 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
     T fb[K], fx[K], fo[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) { fb[a] = T(0); fx[a] = T(0); fo[a] = T(0); }
-    const T pu1 = ju1 * p.icb, pu2 = ju2 * p.icb;       // D / cb factors
+
     // x_prev = c0 D^-1 b:  epre = b (1 - ca c0 / cb) + (1 + ca) x D / cb
     const T opc = T(1) + p.ca, k1 = T(1) - p.ca * p.c0 * p.icb;
     // fetch the epilogue inputs of output plane c of element ee, whose input
     // plane is staged in sU[buf] (fast-path lanes of flushed elements only)
     auto pf_issue = [&](int ee, int c, int buf) __attribute__((always_inline)) {
-        if (pencil_inner && ee >= E0 && ee > 0 && ee < E1) {
+        if (colok && ee >= E0 && ee < E1) {
             const long long zo = (long long)(ee * K + c) * NN;
             const T* U = sU + buf * USZ + (py * K + K) * RX + tx + K;
             cfor<K>([&](auto am) {
                 constexpr int a = decltype(am)::value;
                 const long long ro = zo + (long long)a * N;
-                fb[a] = at(bs, ro);
+                const bool rv = gy0 + a < N;              // rows past the grid: nothing to load
+                fb[a] = rv ? at(bs, ro) : T(0);
                 if (CHEB) {
                     fx[a] = U[a * RX];
-                    fo[a] = xos ? at(xos, ro) : T(0);
+                    fo[a] = (rv && xos) ? at(xos, ro) : T(0);
                 }
             });
         }
@@ -471,8 +475,8 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
                 T e;
                 if (EPI == EPI_RESID) e = fb[a];
                 else if (p.xo_from_b)   // x_prev = c0 D^-1 b
-                    e = fma(fx[a] * opc, jac_s(cm, am, pu1, pu2), fb[a] * k1);
-                else e = fma(fma(p.ca, fx[a] - fo[a], fx[a]), jac_s(cm, am, pu1, pu2), fb[a]);
+                    e = fma(fx[a] * opc, (jac_s(cm, am, ju1, ju2) * p.icb), fb[a] * k1);
+                else e = fma(fma(p.ca, fx[a] - fo[a], fx[a]), (jac_s(cm, am, ju1, ju2) * p.icb), fb[a]);
                 acc[c][a] -= e;
             });
         }
@@ -481,21 +485,28 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
     // Write the K completed output planes of element e.  Per output plane the
     // epilogue loads of its K nodes are issued together before any use.
     auto flush = [&](int e) __attribute__((always_inline)) {
-        if (PF && pencil_inner && e > 0) {
+        if constexpr (PF) {
+            // every column of the tile (boundary nodes written as zero)
+            if (!colok) return;
             cfor<K>([&](auto cm) {
                 constexpr int c = decltype(cm)::value;
-                const long long zo = (long long)(e * K + c) * NN;
+                const int z = e * K + c;
+                const long long zo = (long long)z * NN;
                 cfor<K>([&](auto am) {
                     constexpr int a = decltype(am)::value;
-                    const long long ro = zo + (long long)a * N;
-                    const T d = -acc[c][a];                      // epre - A x
-                    const T out = EPI == EPI_RESID ? d : p.cb * recip(jac(cm, am)) * d;
-                    *reinterpret_cast<T*>(reinterpret_cast<char*>(vs + ro) + colbyte) = out;
+                    const int y = gy0 + a;
+                    if (y < N) {
+                        const long long ro = zo + (long long)a * N;
+                        const bool bnd = z == 0 || xbnd || y == 0 || y >= nK;
+                        const T d = -acc[c][a];                      // epre - A x
+                        const T out = EPI == EPI_RESID ? d : p.cb * recip(jac(cm, am)) * d;
+                        *reinterpret_cast<T*>(reinterpret_cast<char*>(vs + ro) + colbyte) = bnd ? T(0) : out;
+                    }
                 });
             });
             return;
         }
-        if (!PF && pencil_inner && e > 0) {
+        if (pencil_inner && e > 0) {
             cfor<K>([&](auto cm) {
                 constexpr int c = decltype(cm)::value;
                 const long long zo = (long long)(e * K + c) * NN;

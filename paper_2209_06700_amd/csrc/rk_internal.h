@@ -126,9 +126,6 @@ hipError_t launch_gs_update(const double* X, int nvec, long long ld, const doubl
 hipError_t launch_reduce(const double* part, int nblocks, int nout, double* out, int accumulate,
                          hipStream_t st, const double* scale = nullptr, int nscale = 0,
                          double* inv_sqrt_out = nullptr);
-// v = w * (1 / sqrt(*nrm2))
-hipError_t launch_normalize(double* v, const double* w, const double* nrm2, long long n,
-                            hipStream_t st);
 // k += sum_j y[j] Z_j   (Z fp64 or fp32)
 hipError_t launch_combine(double* kv, int dtype_z, const void* Z, int nz, long long ld,
                           const double* y, long long n, hipStream_t st);
