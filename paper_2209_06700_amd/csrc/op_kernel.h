@@ -153,15 +153,14 @@ __device__ __forceinline__ T diag_rt(int r) {
     return d;
 }
 
-// Minimum waves per SIMD requested from the register allocator for the fp32
-// Chebyshev kernels of degree <= 4, which hold the epilogue prefetch (3k
-// values) on top of the operator's registers: four for the general step
-// (measured 13% faster than three), three for the fused first step (which
-// also holds the staging scales and spills at four).  Otherwise the
-// allocator's own choice.
+// Minimum waves per SIMD requested from the register allocator: four for the
+// fp32 Chebyshev kernels of degree <= 4, which hold the epilogue prefetch on
+// top of the operator's registers (measured 13% faster than the three waves
+// the allocator picks by itself, at the cost of a few loop-invariant values
+// spilled outside the march).  Otherwise the allocator's own choice.
 template <int K, typename T, int EPI>
 struct MinWaves {
-    static constexpr int v = (sizeof(T) != 4 || K > 4) ? 1 : EPI == EPI_CHEB ? 4 : EPI == EPI_CHEB1 ? 3 : 1;
+    static constexpr int v = (sizeof(T) == 4 && K <= 4 && (EPI == EPI_CHEB || EPI == EPI_CHEB1)) ? 4 : 1;
 };
 
 template <int K, typename T, int MIX, int EPI>
@@ -448,6 +447,8 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
 
     // x_prev = c0 D^-1 b:  epre = b (1 - ca c0 / cb) + (1 + ca) x D / cb
     const T opc = T(1) + p.ca, k1 = T(1) - p.ca * p.c0 * p.icb;
+    // fused first step (x = c0 D^-1 b, x_prev = 0):  epre = b (1 + (1 + ca) c0 / cb)
+    const T kb1 = T(1) + opc * p.c0 * p.icb;
     // fetch the epilogue inputs of output plane c of element ee, whose input
     // plane is staged in sU[buf] (fast-path lanes of flushed elements only)
     auto pf_issue = [&](int ee, int c, int buf) __attribute__((always_inline)) {
@@ -459,7 +460,7 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
                 const long long ro = zo + (long long)a * N;
                 const bool rv = gy0 + a < N;              // rows past the grid: nothing to load
                 fb[a] = rv ? at(bs, ro) : T(0);
-                if (CHEB) {
+                if (CHEB && !INB) {            // the fused first step needs b only
                     fx[a] = U[a * RX];
                     fo[a] = (rv && xos) ? at(xos, ro) : T(0);
                 }
@@ -474,6 +475,7 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
                 constexpr int a = decltype(am)::value;
                 T e;
                 if (EPI == EPI_RESID) e = fb[a];
+                else if (INB) e = fb[a] * kb1;  // x = c0 D^-1 b, x_prev = 0
                 else if (p.xo_from_b)   // x_prev = c0 D^-1 b
                     e = fma(fx[a] * opc, (jac_s(cm, am, ju1, ju2) * p.icb), fb[a] * k1);
                 else e = fma(fma(p.ca, fx[a] - fo[a], fx[a]), (jac_s(cm, am, ju1, ju2) * p.icb), fb[a]);
