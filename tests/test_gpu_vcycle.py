@@ -31,8 +31,12 @@ def _oracle_mg(n, k, Q, tau, degree, coarse_degree):
     return tab, hier, mg
 
 
+# (n, k, Q, tau, smoother degree, coarse degree): degrees 1..6, smoother
+# degrees 1..4 (1: first iterate only; 2: fused first steps only), odd and
+# even coarse degrees, odd cell counts (single level)
 VCASES = [(8, 2, 2, 0.05, 3, 3), (4, 3, 3, 0.01, 2, 4), (16, 1, 2, 0.1, 3, 3), (6, 2, 1, 0.2, 3, 3),
-          (2, 4, 4, 0.003, 3, 2), (5, 2, 2, 0.05, 3, 3)]
+          (2, 4, 4, 0.003, 3, 2), (5, 2, 2, 0.05, 3, 3), (4, 5, 2, 0.01, 3, 3), (2, 6, 3, 0.005, 2, 3),
+          (8, 4, 2, 0.01, 4, 1), (4, 4, 3, 0.01, 1, 2)]
 
 
 @pytest.mark.parametrize("n,k,Q,tau,deg,cdeg", VCASES)
