@@ -19,6 +19,9 @@ Reported:
   the HBM bytes that the FETCH_SIZE / WRITE_SIZE counters measured;
 * plain_fp64_per_stage: the same steps with the preconditioner in fp64 and
   the Q blocks solved one after another (the unbatched, full-precision form);
+* uneven_batch: 64 independent problems (the seeded mixed batch of meshes,
+  degrees, Q and tau), one step each through rk_step_batch, concurrent on 8
+  streams, against the same steps one after another;
 * host leg (skipped with --no-cpu), the only part that runs the oracle:
   cpu_baseline, the oracle's assembled block operator (scipy CSR SpMV) on a
   bounded sample (16^3 cells, Q_4, same Q and tau), in the same unit; and
@@ -224,6 +227,59 @@ def cpu_baseline_leg(torch, R, n=16, k=4, Q=4, tau=5e-4, budget_s=12.0):
     return cpu, acc
 
 
+BATCH_CELLS = (4, 6, 8, 12, 16, 24, 32, 48)
+
+
+def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20):
+    """The uneven batch: `count` independent heat problems, one Radau IIA step
+    each, drawn with numpy.random.default_rng(seed): n^3 cells with n from
+    4..48 (values with a multigrid hierarchy: n = 2^j or 3 * 2^j), degree
+    U{1..6}, Q U{1..5}, tau log-uniform in [1e-4, 1e-1], mixed precision,
+    seeded Fourier data.  Timed once concurrently (rk_step_batch, one stream
+    and host thread per group of problems) and once one problem after another."""
+    import numpy as np
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
+    rng = np.random.default_rng(seed)
+    probs = []
+    for _ in range(count):
+        n = int(rng.choice(BATCH_CELLS))
+        k = int(rng.integers(1, 7))
+        Q = int(rng.integers(1, 6))
+        tau = float(10 ** rng.uniform(-4, -1))
+        probs.append((n, k, Q, tau))
+    sts = [torch.cuda.Stream() for _ in range(streams)]
+    ctxs = [R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, rtol=1e-10, restart=restart,
+                       stream=sts[i % streams]) for i, (n, k, Q, tau) in enumerate(probs)]
+    y0 = [torch.tensor(fourier_field(grid_coords(c.info["nodes"], n), seed=i), device="cuda")
+          for i, (c, (n, _, _, _)) in enumerate(zip(ctxs, probs))]
+    handles = [c.ctx for c in ctxs]
+    zeros = [0.0] * count
+
+    def run(threads):
+        ys = [y.clone() for y in y0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = R.rk_step_batch(handles, zeros, ys, threads=threads)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st
+
+    run(streams)                                  # warm-up (graph capture, caches)
+    t_conc, st = run(streams)
+    t_seq, _ = run(1)
+    sdofs = sum(Q * (n * k + 1) ** 3 for n, k, Q, _ in probs)
+    its = [s["iterations"] for s in st]
+    for c in ctxs:
+        c.close()
+    del y0
+    torch.cuda.empty_cache()
+    return {"problems": count, "recipe": f"default_rng({seed}): n in {list(BATCH_CELLS)}, k U{{1..6}}, "
+                                         f"Q U{{1..5}}, tau log-uniform [1e-4, 1e-1], mixed, rtol 1e-10, "
+                                         f"restart {restart}",
+            "stage_dofs": sdofs, "streams": streams, "s_concurrent": t_conc, "s_sequential": t_seq,
+            "speedup": t_seq / t_conc, "stage_dof_steps_per_s": sdofs / t_conc,
+            "fgmres_iterations": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
+
+
 def loosest_rtol(acc_runs, bound=1e-8):
     """The loosest FGMRES tolerance whose step error is within `bound`."""
     ok = [float(r) for r, v in acc_runs.items() if v["rel_l2_error"] <= bound]
@@ -238,6 +294,7 @@ def main():
     ap.add_argument("--op-reps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the host leg (oracle)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 per-stage comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven batch of 64 problems")
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--cheb-degree", type=int, default=None, help="smoother degree (library default if unset)")
     ap.add_argument("--cheb-range", type=float, default=None, help="Chebyshev range (library default if unset)")
@@ -337,6 +394,11 @@ def main():
             log(f"[bench] at 1e-8 accuracy: plain fp64 per-stage {tp * 1e3:.2f} ms (rtol {r_plain:.0e})")
     del y0
     torch.cuda.empty_cache()
+    batch = None
+    if not args.no_batch:
+        batch = uneven_batch(torch, R)
+        log(f"[bench] uneven batch of {batch['problems']}: {batch['s_concurrent'] * 1e3:.1f} ms concurrent, "
+            f"{batch['s_sequential'] * 1e3:.1f} ms one after another")
     flop = op_flops_per_stage_dof(k)
     achieved = flop * sdofs / t_blk / 1e12
     hbm_gbs = 8.0 * sdofs / t_blk / 1e9
@@ -365,6 +427,7 @@ def main():
             "ms_per_step": t_plain * 1e3, "fgmres_iterations": its_plain, "rtol": 1e-10,
             "speedup_of_mixed_batched": t_plain / t_step},
         "at_1e-8_accuracy": at_acc,
+        "uneven_batch": batch,
         "step_breakdown_s": {k2: breakdown[k2] for k2 in ("t_rhs", "t_vmult", "t_basis", "t_blocks", "t_rest")},
         "operators": {
             "blocks_fp32_us": t_blk * 1e6,

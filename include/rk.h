@@ -160,6 +160,22 @@ int rk_info(const rk_ctx* ctx, rk_info_t* out);
 int rk_step(rk_ctx* ctx, double t_n, double* d_y, const double* d_G, const double* h_gamma,
             rk_stats* h_stats);
 
+/* One step of each of `count` independent contexts: the uneven batch of heat
+   problems with different meshes, degrees, Q and tau (one context each).
+   Entry i is rk_step(ctx[i], t_n[i], d_y[i], d_G[i], h_gamma + i*RK_MAX_Q,
+   h_stats + i); d_G may be NULL or hold NULL entries, h_stats and h_codes may
+   be NULL.  The entries run concurrently on `threads` host threads (0: one
+   per entry; at most 16): worker w steps entries w, w + threads, ... in
+   order, each on its context's own stream, so entries created on different
+   streams overlap on the GPU (give entry i the stream i mod threads).  A
+   context must appear at most once.  Every entry is attempted; per-entry codes
+   go to h_codes, and the return value is the first failing entry's code
+   (RK_OK if all succeeded).  Errors of an entry are reported by
+   rk_last_error(ctx[i]). */
+int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* const* d_y,
+                  const double* const* d_G, const double* h_gamma, rk_stats* h_stats, int* h_codes,
+                  int threads);
+
 /* v = op(u) for one of the RK_OP_* forms, with dtype RK_FP64 or RK_FP32 for
    both vectors.  Q-stage forms take [Q][N^3] vectors, RK_OP_K / RK_OP_M one
    [N^3] vector.  u and v must not overlap.  Asynchronous. */

@@ -23,7 +23,8 @@ RK_OP_CALA, RK_OP_STAGE, RK_OP_BLOCKS, RK_OP_K, RK_OP_M = 0, 1, 2, 3, 4
 RK_MAX_Q, RK_MAX_DEGREE, RK_MAX_LEVELS = 9, 6, 16
 
 EXPORTS = ["rk_default_options", "rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info",
-           "rk_step", "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner", "rk_last_error"]
+           "rk_step", "rk_step_batch", "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner",
+           "rk_last_error"]
 
 
 class rk_mesh(C.Structure):
@@ -68,12 +69,14 @@ def load():
     lib.rk_destroy.argtypes = [vp]
     lib.rk_info.argtypes = [vp, C.POINTER(rk_info_t)]
     lib.rk_step.argtypes = [vp, C.c_double, vp, vp, C.POINTER(C.c_double), C.POINTER(rk_stats)]
+    lib.rk_step_batch.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_double), C.POINTER(vp), C.POINTER(vp),
+                                  C.POINTER(C.c_double), C.POINTER(rk_stats), C.POINTER(C.c_int), C.c_int]
     lib.rk_apply_operator.argtypes = [vp, C.c_int, C.c_int, vp, vp]
     lib.rk_vcycle.argtypes = [vp, C.c_int, vp, vp]
     lib.rk_apply_preconditioner.argtypes = [vp, vp, vp]
     lib.rk_last_error.argtypes = [vp]
     lib.rk_last_error.restype = C.c_char_p
-    for name in ("rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info", "rk_step",
+    for name in ("rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info", "rk_step", "rk_step_batch",
                  "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner"):
         getattr(lib, name).restype = C.c_int
     return lib

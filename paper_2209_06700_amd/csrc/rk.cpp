@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rk_internal.h"
@@ -99,6 +100,7 @@ struct rk_ctx {
     Tableau tab{};
     Element1D el{};
     hipStream_t stream = nullptr;
+    int device = 0;                // HIP device current at create
     // The fine-level V-cycle (F.b -> F.x, fixed buffers) is captured once into
     // a HIP graph on a private stream and replayed on `stream`: the coarse
     // levels are tens of small launches whose dispatch cost the graph cuts.
@@ -628,6 +630,7 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
     if (((uintptr_t)d_workspace) % kAlign) { delete c; return fail(nullptr, RK_EINVAL, "workspace not 256-byte aligned"); }
     carve(*c, (char*)d_workspace);
     c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return fail(nullptr, RK_EHIP, "no HIP device"); }
     c->host_scal.assign(c->opt.restart + 16, 0.0);
     std::string msg;
     if (!build_tableau(Q, c->tab, msg)) { delete c; return fail(nullptr, RK_EINVAL, msg); }
@@ -845,6 +848,44 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
     if (stats) *stats = st;
     if (!converged) return fail(c, RK_ENOCONV, "FGMRES did not reach rtol within max_iter");
     return RK_OK;
+}
+
+int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* const* y, const double* const* G,
+                  const double* gamma, rk_stats* stats, int* codes, int threads) {
+    if (count < 0 || (count > 0 && (!ctx || !t_n || !y))) return fail(nullptr, RK_EINVAL, "bad batch arguments");
+    for (int i = 0; i < count; ++i) {
+        if (!ctx[i] || !y[i]) return fail(nullptr, RK_EINVAL, "NULL context or vector in the batch");
+        if (G && G[i] && !gamma) return fail(nullptr, RK_EINVAL, "gamma is NULL while G is given");
+        for (int j = 0; j < i; ++j)
+            if (ctx[j] == ctx[i]) return fail(nullptr, RK_EINVAL, "a context appears twice in the batch");
+    }
+    if (count == 0) return RK_OK;
+    int nt = threads > 0 ? threads : count;
+    nt = std::max(1, std::min(std::min(nt, count), 16));
+    std::vector<int> rc(count, RK_OK);
+    // worker w steps entries w, w + nt, ... in order (contexts that share a
+    // stream should share a worker: give entry i the stream i mod nt)
+    auto work = [&](int w) {
+        for (int i = w; i < count; i += nt) {
+            if (hipSetDevice(ctx[i]->device) != hipSuccess) { rc[i] = fail(ctx[i], RK_EHIP, "hipSetDevice failed"); continue; }
+            rc[i] = rk_step(ctx[i], t_n[i], y[i], G ? G[i] : nullptr, gamma ? gamma + (size_t)i * RK_MAX_Q : nullptr,
+                            stats ? stats + i : nullptr);
+        }
+    };
+    if (nt == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> pool;
+        pool.reserve(nt);
+        for (int w = 0; w < nt; ++w) pool.emplace_back(work, w);
+        for (auto& t : pool) t.join();
+    }
+    int first = RK_OK;
+    for (int i = 0; i < count; ++i) {
+        if (codes) codes[i] = rc[i];
+        if (first == RK_OK && rc[i] != RK_OK) first = rc[i];
+    }
+    return first;
 }
 
 const char* rk_last_error(const rk_ctx* c) {

@@ -14,11 +14,12 @@ import torch
 
 from . import _lib
 from ._lib import (LIB, RK_BATCHED, RK_ENOCONV, RK_FP32, RK_FP64, RK_OK, RK_OP_BLOCKS, RK_OP_CALA,
-                   RK_OP_K, RK_OP_M, RK_OP_STAGE, RK_PER_STAGE, RK_PREC_FP64, RK_PREC_MIXED,
+                   RK_MAX_Q, RK_OP_K, RK_OP_M, RK_OP_STAGE, RK_PER_STAGE, RK_PREC_FP64, RK_PREC_MIXED,
                    rk_info_t, rk_mesh, rk_options, rk_stats)
 
 __all__ = ["RKError", "rk_default_options", "rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info",
-           "rk_step", "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner", "rk_last_error",
+           "rk_step", "rk_step_batch", "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner",
+           "rk_last_error",
            "RadauIIA", "RK_FP64", "RK_FP32", "RK_PREC_FP64", "RK_PREC_MIXED", "RK_BATCHED",
            "RK_PER_STAGE", "RK_OP_CALA", "RK_OP_STAGE", "RK_OP_BLOCKS", "RK_OP_K", "RK_OP_M"]
 
@@ -161,9 +162,44 @@ def rk_step(ctx: Context, t_n: float, y: torch.Tensor, G: torch.Tensor | None = 
     rc = LIB.rk_step(ctx.handle, float(t_n), yp, gp, garr, C.byref(st))
     if rc != RK_OK and not (rc == RK_ENOCONV and not raise_on_noconv):
         raise RKError(rc, rk_last_error(ctx))
+    return _stats_dict(rc, st)
+
+
+def _stats_dict(rc, st):
     return dict(code=rc, iterations=st.iterations, vcycles=st.vcycles, rel_residual=st.rel_residual,
                 t_rhs=st.t_rhs, t_vmult=st.t_vmult, t_basis=st.t_basis, t_blocks=st.t_blocks,
                 t_rest=st.t_rest)
+
+
+def rk_step_batch(ctxs, t_n, ys, Gs=None, gammas=None, threads: int = 0, raise_on_error: bool = True):
+    """One step of each context (rk_step_batch): ctxs, t_n, ys (fp64 N_i^3
+    tensors) and optionally Gs / gammas are sequences of equal length.
+    Returns the per-entry stats dicts (with the entry's code)."""
+    m = len(ctxs)
+    if not (len(t_n) == len(ys) == m) or (Gs is not None and len(Gs) != m):
+        raise ValueError("batch sequences must have equal lengths")
+    handles = (C.c_void_p * m)(*[c.handle for c in ctxs])
+    tarr = (C.c_double * m)(*[float(t) for t in t_n])
+    yarr = (C.c_void_p * m)(*[_vec(y, c.N ** 3, "y", torch.float64) for c, y in zip(ctxs, ys)])
+    garr = None
+    gam = (C.c_double * (m * RK_MAX_Q))()
+    if Gs is not None:
+        garr = (C.c_void_p * m)(*[None if G is None else _vec(G, c.N ** 3, "G", torch.float64)
+                                  for c, G in zip(ctxs, Gs)])
+        for i, (c, G) in enumerate(zip(ctxs, Gs)):
+            if G is not None:
+                if gammas is None or gammas[i] is None or len(gammas[i]) != c.Q:
+                    raise ValueError(f"entry {i}: gamma must hold Q values")
+                for q, g in enumerate(gammas[i]):
+                    gam[i * RK_MAX_Q + q] = float(g)
+    st = (rk_stats * m)()
+    codes = (C.c_int * m)()
+    rc = LIB.rk_step_batch(handles, m, tarr, yarr, garr, gam, st, codes, int(threads))
+    out = [_stats_dict(codes[i], st[i]) for i in range(m)]
+    if rc != RK_OK and raise_on_error:
+        bad = next(i for i in range(m) if codes[i] != RK_OK)
+        raise RKError(rc, f"entry {bad}: {rk_last_error(ctxs[bad])}")
+    return out
 
 
 def rk_apply_operator(ctx: Context, form: int, u: torch.Tensor, v: torch.Tensor):

@@ -81,3 +81,16 @@ def test_create_rejects_missing_workspace_without_touching_the_gpu():
     assert b"workspace" in lib.rk_last_error(None)
     rc = lib.rk_create(C.byref(mesh), 2, 2, -1.0, None, None, 0, None, C.byref(out))
     assert rc == _lib.RK_EINVAL
+
+
+def test_step_batch_argument_checks_without_the_gpu():
+    """rk_step_batch validates its arguments before any context is touched:
+    an empty batch succeeds, NULL entries are rejected."""
+    from paper_2209_06700_amd import _lib
+    L = _lib.LIB
+    assert L.rk_step_batch(None, 0, None, None, None, None, None, None, 0) == _lib.RK_OK
+    ctx = (C.c_void_p * 1)(None)
+    t = (C.c_double * 1)(0.0)
+    y = (C.c_void_p * 1)(None)
+    assert L.rk_step_batch(ctx, 1, t, y, None, None, None, None, 1) == _lib.RK_EINVAL
+    assert L.rk_step_batch(ctx, -1, t, y, None, None, None, None, 1) == _lib.RK_EINVAL

@@ -1,0 +1,79 @@
+"""The uneven batch: one Radau IIA step of many independent heat problems
+(different meshes, degrees, Q, tau and precisions) through rk_step_batch,
+each context on its own stream, stepped concurrently from several host
+threads.  Every entry must equal the same step taken alone (bitwise: the same
+kernels run in the same order per context) and match the modal oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2209_06700_amd import rk
+    return rk
+
+
+# (n, k, Q, tau, precision)
+PROBLEMS = [(4, 3, 2, 0.02, "fp64"), (6, 2, 3, 0.005, "mixed"), (8, 1, 1, 0.1, "fp64"),
+            (2, 5, 4, 0.001, "mixed"), (12, 2, 5, 0.01, "mixed"), (4, 6, 2, 0.003, "fp64"),
+            (8, 4, 3, 0.0005, "mixed"), (5, 2, 2, 0.05, "fp64")]
+
+
+def _make(R, n, k, Q, tau, prec, stream=None, **kw):
+    p = R.RK_PREC_FP64 if prec == "fp64" else R.RK_PREC_MIXED
+    # rtol 1e-12: the coarse, stiff entries (tau h^-2 up to 6) need it for the
+    # 1e-10 error bar against the exact step
+    return R.RadauIIA(n, k, Q, tau, precision=p, rtol=1e-12, stream=stream, **kw)
+
+
+def _y0(R, s, n, seed):
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
+    return torch.tensor(fourier_field(grid_coords(s.info["nodes"], n), seed=seed), device="cuda")
+
+
+@pytest.mark.parametrize("threads", [1, 3])
+def test_batch_equals_single_steps_and_oracle(R, threads):
+    from oracle.step import ModalSolver
+    from oracle.tableau import RadauIIA
+    print(f"uneven batch of {len(PROBLEMS)}, {threads} threads", flush=True)
+    streams = [torch.cuda.Stream() for _ in range(threads)]
+    ctxs = [_make(R, *pb, stream=streams[i % threads]) for i, pb in enumerate(PROBLEMS)]
+    ys = [_y0(R, s, pb[0], i) for i, (s, pb) in enumerate(zip(ctxs, PROBLEMS))]
+    y_init = [y.clone() for y in ys]
+    torch.cuda.synchronize()
+    stats = R.rk_step_batch([s.ctx for s in ctxs], [0.0] * len(ctxs), ys, threads=threads)
+    torch.cuda.synchronize()
+    for i, ((n, k, Q, tau, prec), s, y, y0, st) in enumerate(zip(PROBLEMS, ctxs, ys, y_init, stats)):
+        alone = _make(R, n, k, Q, tau, prec)
+        ya = y0.clone()
+        sa = alone.step(0.0, ya)
+        assert sa["iterations"] == st["iterations"], i
+        assert torch.equal(ya, y), f"entry {i} differs from the single step"
+        N = n * k + 1
+        inner = lambda v: v.reshape(N, N, N)[1:-1, 1:-1, 1:-1].reshape(-1)
+        ref = ModalSolver(n, k).step(RadauIIA(Q), tau, inner(y0.cpu().numpy()))
+        err = float(np.linalg.norm(inner(y.cpu().numpy()) - ref) / np.linalg.norm(ref))
+        assert err <= (1e-10 if prec == "fp64" else 1e-8), (i, err)
+        alone.close()
+        s.close()
+
+
+def test_batch_entry_failure_is_isolated(R):
+    """An entry that reaches max_iter reports RK_ENOCONV and keeps its y; the
+    other entries still step."""
+    good = _make(R, 4, 2, 2, 0.01, "fp64")
+    bad = R.RadauIIA(4, 2, 3, 0.5, rtol=1e-15, max_iter=2, restart=2)
+    yg, yb = _y0(R, good, 4, 0), _y0(R, bad, 4, 1)
+    yb0 = yb.clone()
+    st = R.rk_step_batch([good.ctx, bad.ctx], [0.0, 0.0], [yg, yb], threads=2, raise_on_error=False)
+    assert st[0]["code"] == 0 and st[1]["code"] == R._lib.RK_ENOCONV
+    assert torch.equal(yb, yb0)
+    with pytest.raises(R.RKError):
+        R.rk_step_batch([good.ctx, bad.ctx], [0.0, 0.0], [yg, yb], threads=2)
+    good.close()
+    bad.close()
