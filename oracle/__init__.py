@@ -23,6 +23,9 @@ multigrid  Chebyshev-Jacobi smoother, geometric multigrid V-cycle and the
            stage-block preconditioner P^-1 (eq. irk:P, Sec. 5).
 fgmres     right-preconditioned flexible GMRES on the premultiplied stage
            operator (eq. irk:A).
+complex_irk  direct diagonalisation A_Q^-1 = S Lam S^-1 (eq. irk:Ainv) in
+           real two-by-two form, the PRESB preconditioner (Sec. 6) and the
+           step that solves every block with its own GMRES.
 pointwise  single rows of the assembled operators, for sampled checks on
            meshes too large to assemble.
 """
