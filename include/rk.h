@@ -16,6 +16,23 @@
  *   with a Chebyshev-Jacobi smoother and a Chebyshev coarse solve (Sec. 5).
  *   Then y_{n+1} = y_n + tau sum_i b_i k_i (Sec. 1).
  *
+ *   The alternative of Sec. 6 (rk_options.method = RK_METHOD_COMPLEX)
+ *   diagonalises A_Q^-1 = S Lam S^-1 directly (eq. irk:Ainv; complex S,
+ *   Lam) and solves the ceil(Q/2) blocks lam_i M + tau K independently, one
+ *   GMRES per block, written as two-by-two real systems
+ *   [[K', -M'], [M', K']] with K' = Re(lam) M + tau K, M' = Im(lam) M
+ *   (eq. complex:twobytwo) and preconditioned by PRESB (eq. presb:p): two
+ *   V-cycles in sequence on H = (Re lam + Im lam) M + tau K.
+ *
+ * Slot layout of the complex method (RK_OP_CBLOCKS, rk_apply_preconditioner
+ *   and rk_vcycle of an RK_METHOD_COMPLEX context): a [Q][N^3] vector of
+ *   "slots".  With nb = ceil(Q/2) blocks (the floor(Q/2) conjugate pairs, one
+ *   member each with Im lam > 0 in ascending Re lam, then the real
+ *   eigenvalue for odd Q), slots 0..nb-1 hold the real parts of the pair
+ *   unknowns and the real block, slots nb..Q-1 the imaginary parts: pair j
+ *   owns slots j and nb + j.  slots = (T (x) I) k and k = (U (x) I) slots
+ *   with the real Q x Q matrices T = U^-1 of rk_info_t.
+ *
  * Vector layout (every vector argument):
  *   full grid of N = n_cells*degree + 1 nodes per direction, node (ix,iy,iz)
  *   at offset ix + N*(iy + N*iz) (x fastest); Q-stage vectors are stage-major,
@@ -69,12 +86,18 @@ extern "C" {
 #define RK_BATCHED   0     /* all Q blocks in every kernel launch (Sec. 3, batching) */
 #define RK_PER_STAGE 1     /* one block after the other (the paper's sequential IRK) */
 
+/* stage-system solver (rk_options.method) */
+#define RK_METHOD_CROUT   0   /* FGMRES on eq. (irk:A) with the preconditioner of eq. (irk:P) */
+#define RK_METHOD_COMPLEX 1   /* direct diagonalisation, per-block GMRES with PRESB (Sec. 6)  */
+
 /* operator forms for rk_apply_operator */
 #define RK_OP_CALA   0     /* v = (A^-1 (x) M + tau I (x) K) u, Q stages, eq. (irk:A) */
 #define RK_OP_STAGE  1     /* v = (I (x) M + tau A (x) K) u,    Q stages (stage system, Sec. 2) */
 #define RK_OP_BLOCKS 2     /* v_i = (lam_i M + tau K) u_i,      Q stages, blocks of eq. (irk:P) */
 #define RK_OP_K      3     /* v = K u, one vector */
 #define RK_OP_M      4     /* v = M u, one vector */
+#define RK_OP_CBLOCKS 5    /* v = (Lam_r (x) M + tau I (x) K) u on slot vectors: per pair
+                              [[K', -M'], [M', K']], the real block lam M + tau K (Sec. 6) */
 
 #define RK_MAX_Q      9
 #define RK_MAX_DEGREE 6
@@ -103,14 +126,19 @@ typedef struct {
     const double* eig_max;      /* host [n_levels]: explicit upper bounds (fine to
                                    coarse), used as given; NULL = estimate at create */
     int32_t timing;             /* 1: fill the per-component times of rk_stats     */
+    int32_t method;             /* RK_METHOD_CROUT | RK_METHOD_COMPLEX              */
 } rk_options;
 
 typedef struct {
-    int32_t iterations;         /* FGMRES iterations of the step                    */
+    int32_t iterations;         /* FGMRES iterations of the step (complex method:
+                                   lock-step iterations, the maximum over blocks)   */
     int32_t vcycles;            /* V-cycles (counted per block solve when per-stage,
                                    per batched launch sequence when batched)         */
-    double  rel_residual;       /* true ||rhs - A k||_2 / ||rhs||_2 at the end      */
+    double  rel_residual;       /* true ||rhs - A k||_2 / ||rhs||_2 at the end (complex
+                                   method: the largest block's relative residual)   */
     double  t_rhs, t_vmult, t_basis, t_blocks, t_rest;   /* seconds (timing = 1)     */
+    int32_t block_iterations[RK_MAX_Q];   /* complex method: GMRES iterations of
+                                   block j (j < n_blocks); zero otherwise            */
 } rk_stats;
 
 typedef struct {
@@ -125,11 +153,16 @@ typedef struct {
     double  lambda[RK_MAX_Q];             /* Lam = diag(L)                          */
     double  eig_max[RK_MAX_LEVELS];       /* Chebyshev upper bounds in use          */
     double  nodes[RK_MAX_DEGREE + 1];     /* Gauss-Lobatto nodes on [0,1]           */
+    /* direct diagonalisation of A^-1 (eq. irk:Ainv) in the slot layout above   */
+    int32_t n_blocks, n_pairs;            /* ceil(Q/2), floor(Q/2)                  */
+    double  clam_re[RK_MAX_Q], clam_im[RK_MAX_Q];   /* lam of block j (Im >= 0)     */
+    double  T[RK_MAX_Q * RK_MAX_Q], U[RK_MAX_Q * RK_MAX_Q];   /* row-major, T = U^-1 */
 } rk_info_t;
 
 /* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
    max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
-   cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0. */
+   cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0,
+   RK_METHOD_CROUT. */
 void rk_default_options(rk_options* opt);
 
 /* Bytes of device workspace needed for the given mesh, degree (1..6),
@@ -138,8 +171,10 @@ int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options*
                        size_t* bytes);
 
 /* Sets up a context: Radau IIA tableau (Sec. 2), A^-1 = L U, L = S Lam S^-1
-   (eq. irk:P), 1D element data, the level hierarchy, and the Chebyshev bounds
-   (estimated by power iteration on D^-1 A of every block unless
+   (eq. irk:P), the direct diagonalisation of A^-1 (eq. irk:Ainv), 1D element
+   data, the level hierarchy, and the Chebyshev bounds (estimated by power
+   iteration on D^-1 A of every multigrid block -- lam_i M + tau K, or for
+   RK_METHOD_COMPLEX the PRESB matrices H of every slot -- unless
    opt->eig_max is given; batched and per-stage runs share the largest bound
    over the blocks of a level, as in the paper's batched runs).  d_workspace:
    device memory of at least rk_workspace_bytes() bytes, 256-byte aligned.
@@ -156,7 +191,12 @@ int rk_info(const rk_ctx* ctx, rk_info_t* out);
    y_{n+1} on output.  The source is g(t) = gamma(t) G: d_G is an fp64 [N^3]
    load vector (int f phi_i; NULL means g = 0) and h_gamma a host array of Q
    values gamma(t_n + c_i tau) (ignored when d_G is NULL).  h_stats may be NULL.
-   Returns RK_ENOCONV (y unchanged, stats filled) when max_iter is reached. */
+   Returns RK_ENOCONV (y unchanged, stats filled) when max_iter is reached.
+   RK_METHOD_COMPLEX: the right-hand side of eq. (irk:A) goes to the slots
+   (T (x) I), every block runs its own right-preconditioned GMRES with PRESB
+   until ||w_j - B_j u_j||_2 <= rtol ||w_j||_2 (all blocks advance in lock
+   step, in the same kernel launches; a converged block stops contributing),
+   and k = (U (x) I) u. */
 int rk_step(rk_ctx* ctx, double t_n, double* d_y, const double* d_G, const double* h_gamma,
             rk_stats* h_stats);
 
@@ -182,13 +222,16 @@ int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* cons
 int rk_apply_operator(rk_ctx* ctx, int form, int dtype, const void* d_u, void* d_v);
 
 /* x_i = one V-cycle for the block lam_i M + tau K applied to b_i, i = 1..Q,
-   on [Q][N^3] vectors.  dtype must be RK_FP32 for RK_PREC_MIXED contexts and
+   on [Q][N^3] vectors (RK_METHOD_COMPLEX: for the PRESB matrix H of slot i).  dtype must be RK_FP32 for RK_PREC_MIXED contexts and
    RK_FP64 otherwise.  Batched or per-stage as set in the options.  b and x
    must not overlap.  Asynchronous. */
 int rk_vcycle(rk_ctx* ctx, int dtype, const void* d_b, void* d_x);
 
 /* z = P^-1 r (eq. irk:P) on fp64 [Q][N^3] vectors: basis change S^-1 (with
    the cast to fp32 in mixed precision), the Q block V-cycles, basis change S.
+   RK_METHOD_COMPLEX: z = PRESB^-1 r on slot vectors (eq. presb:p), per pair
+   g1 = V(H)(r_re + r_im), g2 = V(H)(r_im - Im(lam) M g1), z = (g1 - g2, g2),
+   the real block z = V(lam M + tau K) r.
    r and z must not overlap.  Asynchronous. */
 int rk_apply_preconditioner(rk_ctx* ctx, const double* d_r, double* d_z);
 

@@ -19,7 +19,8 @@ RK_OK, RK_EINVAL, RK_EWORKSPACE, RK_EHIP, RK_ENOCONV = 0, -1, -2, -3, -4
 RK_FP64, RK_FP32 = 0, 1
 RK_PREC_FP64, RK_PREC_MIXED = 0, 1
 RK_BATCHED, RK_PER_STAGE = 0, 1
-RK_OP_CALA, RK_OP_STAGE, RK_OP_BLOCKS, RK_OP_K, RK_OP_M = 0, 1, 2, 3, 4
+RK_METHOD_CROUT, RK_METHOD_COMPLEX = 0, 1
+RK_OP_CALA, RK_OP_STAGE, RK_OP_BLOCKS, RK_OP_K, RK_OP_M, RK_OP_CBLOCKS = 0, 1, 2, 3, 4, 5
 RK_MAX_Q, RK_MAX_DEGREE, RK_MAX_LEVELS = 9, 6, 16
 
 EXPORTS = ["rk_default_options", "rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info",
@@ -36,13 +37,14 @@ class rk_options(C.Structure):
                 ("max_iter", C.c_int32), ("restart", C.c_int32), ("cheb_degree", C.c_int32),
                 ("coarse_cheb_degree", C.c_int32), ("cheb_range", C.c_double),
                 ("eig_safety", C.c_double), ("eig_iterations", C.c_int32),
-                ("eig_max", C.POINTER(C.c_double)), ("timing", C.c_int32)]
+                ("eig_max", C.POINTER(C.c_double)), ("timing", C.c_int32), ("method", C.c_int32)]
 
 
 class rk_stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("vcycles", C.c_int32), ("rel_residual", C.c_double),
                 ("t_rhs", C.c_double), ("t_vmult", C.c_double), ("t_basis", C.c_double),
-                ("t_blocks", C.c_double), ("t_rest", C.c_double)]
+                ("t_blocks", C.c_double), ("t_rest", C.c_double),
+                ("block_iterations", C.c_int32 * RK_MAX_Q)]
 
 
 class rk_info_t(C.Structure):
@@ -52,7 +54,10 @@ class rk_info_t(C.Structure):
                 ("A", C.c_double * 81), ("b", C.c_double * 9), ("c", C.c_double * 9),
                 ("Ainv", C.c_double * 81), ("L", C.c_double * 81), ("S", C.c_double * 81),
                 ("Sinv", C.c_double * 81), ("lambda_", C.c_double * 9),
-                ("eig_max", C.c_double * RK_MAX_LEVELS), ("nodes", C.c_double * (RK_MAX_DEGREE + 1))]
+                ("eig_max", C.c_double * RK_MAX_LEVELS), ("nodes", C.c_double * (RK_MAX_DEGREE + 1)),
+                ("n_blocks", C.c_int32), ("n_pairs", C.c_int32),
+                ("clam_re", C.c_double * RK_MAX_Q), ("clam_im", C.c_double * RK_MAX_Q),
+                ("T", C.c_double * 81), ("U", C.c_double * 81)]
 
 
 def load():

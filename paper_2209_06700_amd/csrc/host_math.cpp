@@ -1,7 +1,10 @@
 // Host-side set-up mathematics: the Radau IIA tableau, the Crout factor of
-// A^-1 and its eigen-decomposition (Sec. 2, eq. irk:P) in long double, and the
-// 1D Q_k element data (Sec. 5 set-up) from the compile-time tables.
+// A^-1 and its eigen-decomposition (Sec. 2, eq. irk:P), the direct complex
+// diagonalisation of A^-1 (eq. irk:Ainv) in long double, and the 1D Q_k
+// element data (Sec. 5 set-up) from the compile-time tables.
+#include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <string>
 
@@ -85,6 +88,152 @@ bool invert(int n, const ld* a, ld* inv) {
     return true;
 }
 
+using cld = std::complex<ld>;
+
+// Solves (a - shift I) x = rhs in place (x <- rhs) by Gaussian elimination
+// with partial pivoting; returns the determinant of (a - shift I).  A zero
+// pivot is replaced by a tiny one (inverse iteration at an exact eigenvalue).
+cld shifted_solve(int n, const ld* a, cld shift, cld* x) {
+    cld m[RK_MAX_Q][RK_MAX_Q];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) m[i][j] = cld(a[i * n + j]) - (i == j ? shift : cld(0));
+    cld det = 1;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::abs(m[r][c]) > std::abs(m[piv][c])) piv = r;
+        if (piv != c) {
+            for (int j = 0; j < n; ++j) std::swap(m[piv][j], m[c][j]);
+            if (x) std::swap(x[piv], x[c]);
+            det = -det;
+        }
+        if (m[c][c] == cld(0)) m[c][c] = cld(1e-30L);
+        det *= m[c][c];
+        for (int r = c + 1; r < n; ++r) {
+            const cld f = m[r][c] / m[c][c];
+            for (int j = c; j < n; ++j) m[r][j] -= f * m[c][j];
+            if (x) x[r] -= f * x[c];
+        }
+    }
+    if (x)
+        for (int i = n - 1; i >= 0; --i) {
+            cld acc = x[i];
+            for (int j = i + 1; j < n; ++j) acc -= m[i][j] * x[j];
+            x[i] = acc / m[i][i];
+        }
+    return det;
+}
+
+// Eigenvalues of a (n x n) as the roots of the monic p(z) = det(z I - a),
+// evaluated by elimination, with the Weierstrass (Durand-Kerner) iteration
+// z_i <- z_i - p(z_i) / prod_{j != i} (z_i - z_j).
+bool eigenvalues(int n, const ld* a, cld* z) {
+    ld rad = 0;   // infinity norm bounds every eigenvalue
+    for (int i = 0; i < n; ++i) {
+        ld row = 0;
+        for (int j = 0; j < n; ++j) row += std::fabs(a[i * n + j]);
+        rad = std::max(rad, row);
+    }
+    const cld seed(0.4L, 0.9L);
+    cld p = 1;
+    for (int i = 0; i < n; ++i) { z[i] = rad * p; p *= seed; }
+    ld change = 0;
+    for (int it = 0; it < 2000; ++it) {
+        change = 0;
+        for (int i = 0; i < n; ++i) {
+            // det(z I - a) = (-1)^n det(a - z I)
+            cld pz = shifted_solve(n, a, z[i], nullptr);
+            if (n % 2) pz = -pz;
+            cld den = 1;
+            for (int j = 0; j < n; ++j)
+                if (j != i) den *= z[i] - z[j];
+            if (den == cld(0)) den = cld(1e-30L);
+            const cld dz = pz / den;
+            z[i] -= dz;
+            change = std::max(change, std::abs(dz) / std::max(std::abs(z[i]), (ld)1e-30L));
+        }
+        if (change < 1e-17L) return true;
+    }
+    // the determinant's rounding error stalls the last digits for larger n
+    return change < 1e-13L;
+}
+
+// Right eigenvector for the eigenvalue lam by three steps of inverse
+// iteration, scaled so that its largest component is 1.
+void eigenvector(int n, const ld* a, cld lam, cld* v) {
+    for (int i = 0; i < n; ++i) v[i] = cld(1.0L + 0.1L * i, 0.05L * i);
+    for (int it = 0; it < 3; ++it) {
+        shifted_solve(n, a, lam, v);
+        int im = 0;
+        for (int i = 1; i < n; ++i)
+            if (std::abs(v[i]) > std::abs(v[im])) im = i;
+        const cld s = v[im];
+        for (int i = 0; i < n; ++i) v[i] /= s;
+    }
+}
+
+// The real slot form of the direct diagonalisation of Ai = A^-1.
+bool build_complex(int Q, const ld* Ai, Tableau& t, std::string& err) {
+    cld z[RK_MAX_Q];
+    if (!eigenvalues(Q, Ai, z)) { err = "eigenvalues of A^-1 did not converge"; return false; }
+    ld scale = 0;
+    for (int i = 0; i < Q; ++i) scale = std::max(scale, std::abs(z[i]));
+    cld pairs[RK_MAX_Q];
+    int np = 0, nr = 0;
+    cld real = 0;
+    for (int i = 0; i < Q; ++i) {
+        if (std::fabs(z[i].imag()) <= 1e-12L * scale) { real = cld(z[i].real(), 0); ++nr; }
+        else if (z[i].imag() > 0) pairs[np++] = z[i];
+    }
+    if (nr != Q % 2 || 2 * np + nr != Q) { err = "unexpected spectrum of A^-1"; return false; }
+    std::sort(pairs, pairs + np, [](const cld& x, const cld& y) { return x.real() < y.real(); });
+    const int nb = np + nr;
+    ld U[RK_MAX_Q * RK_MAX_Q] = {0}, T[RK_MAX_Q * RK_MAX_Q];
+    cld v[RK_MAX_Q];
+    for (int j = 0; j < np; ++j) {
+        eigenvector(Q, Ai, pairs[j], v);
+        for (int r = 0; r < Q; ++r) {
+            U[r * Q + j] = 2 * v[r].real();
+            U[r * Q + nb + j] = -2 * v[r].imag();
+        }
+    }
+    if (nr) {
+        eigenvector(Q, Ai, real, v);
+        for (int r = 0; r < Q; ++r) U[r * Q + np] = v[r].real();
+    }
+    if (!invert(Q, U, T)) { err = "eigenvector matrix of A^-1 singular"; return false; }
+    ld L[RK_MAX_Q * RK_MAX_Q] = {0};
+    for (int j = 0; j < np; ++j) {
+        const ld a = pairs[j].real(), b = pairs[j].imag();
+        L[j * Q + j] = a; L[j * Q + nb + j] = -b;
+        L[(nb + j) * Q + j] = b; L[(nb + j) * Q + nb + j] = a;
+    }
+    if (nr) L[np * Q + np] = real.real();
+    // check T A^-1 U = Lam_r
+    ld dev = 0;
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j) {
+            ld acc = 0;
+            for (int l = 0; l < Q; ++l)
+                for (int m = 0; m < Q; ++m) acc += T[i * Q + l] * Ai[l * Q + m] * U[m * Q + j];
+            dev = std::max(dev, std::fabs(acc - L[i * Q + j]));
+        }
+    if (!(dev <= 1e-10L * scale)) { err = "direct diagonalisation of A^-1 inaccurate"; return false; }
+    t.nb = nb;
+    t.npair = np;
+    for (int j = 0; j < RK_MAX_Q; ++j) { t.clam_re[j] = 0; t.clam_im[j] = 0; t.hshift[j] = 0; }
+    for (int j = 0; j < np; ++j) {
+        t.clam_re[j] = (double)pairs[j].real();
+        t.clam_im[j] = (double)pairs[j].imag();
+        t.hshift[j] = t.hshift[nb + j] = (double)(pairs[j].real() + pairs[j].imag());
+    }
+    if (nr) { t.clam_re[np] = (double)real.real(); t.hshift[np] = (double)real.real(); }
+    for (int i = 0; i < Q * Q; ++i) {
+        t.CT[i] = (double)T[i]; t.CU[i] = (double)U[i]; t.CLam[i] = (double)L[i];
+    }
+    return true;
+}
+
 }  // namespace
 
 bool build_tableau(int Q, Tableau& t, std::string& err) {
@@ -160,7 +309,7 @@ bool build_tableau(int Q, Tableau& t, std::string& err) {
         t.S[i] = (double)S[i]; t.Sinv[i] = (double)Si[i];
     }
     for (int i = 0; i < Q; ++i) t.lam[i] = (double)L[i * Q + i];
-    return true;
+    return build_complex(Q, Ai, t, err);
 }
 
 namespace {

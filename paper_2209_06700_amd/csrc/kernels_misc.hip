@@ -125,8 +125,11 @@ __global__ void __launch_bounds__(kBlock) stage_mix_kernel(const Tin* __restrict
                                                            const double* __restrict__ D, int qout,
                                                            int qin, int N, double* __restrict__ out2,
                                                            const double* __restrict__ D2,
-                                                           const double* __restrict__ in_scale) {
-    const double isc = in_scale ? *in_scale : 1.0;
+                                                           const double* __restrict__ in_scale,
+                                                           SlotIdx sidx) {
+    double isc[RK_MAX_Q];
+#pragma unroll
+    for (int j = 0; j < RK_MAX_Q; ++j) isc[j] = (in_scale && j < qin) ? in_scale[sidx.v[j]] : 1.0;
     const int nK = N - 1;
     const long long N3 = (long long)N * N * N;
     for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N3;
@@ -137,7 +140,7 @@ __global__ void __launch_bounds__(kBlock) stage_mix_kernel(const Tin* __restrict
         const bool inner = x > 0 && x < nK && y > 0 && y < nK && z > 0 && z < nK;
         double u[RK_MAX_Q];
 #pragma unroll
-        for (int j = 0; j < RK_MAX_Q; ++j) u[j] = (j < qin && inner) ? isc * (double)in[(long long)j * N3 + r] : 0.0;
+        for (int j = 0; j < RK_MAX_Q; ++j) u[j] = (j < qin && inner) ? isc[j] * (double)in[(long long)j * N3 + r] : 0.0;
 #pragma unroll
         for (int i = 0; i < RK_MAX_Q; ++i) {
             if (i >= qout) break;
@@ -225,38 +228,52 @@ struct Pair<double> { using type = double2; };
 template <>
 struct Pair<float> { using type = float2; };
 
-// part[blk * nout + l0 + u] = sum over the block's entries of X_u[i] w[i]
-// (u < NV), and if self: part[blk * nout + l0 + NV] = sum w[i]^2.
+// Segment loop helper: calls f2(i) for the 16-byte aligned pairs (i, i+1) of
+// the segment [o, o + n) that fall to this thread (grid-stride), and f1(i)
+// on thread 0 for the unpaired head (odd o) and tail elements.
+template <bool V2, typename F2, typename F1>
+__device__ __forceinline__ void seg_loop(long long o, long long n, long long tid, long long step, F2&& f2,
+                                         F1&& f1) {
+    if constexpr (V2) {
+        if ((o & 1) && n > 0) {
+            if (tid == 0) f1(o);
+            ++o;
+            --n;
+        }
+        const long long n2 = n >> 1;
+        for (long long i = tid; i < n2; i += step) f2(o + 2 * i);
+        if ((n & 1) && tid == 0) f1(o + n - 1);
+    } else {
+        for (long long i = tid; i < n; i += step) f1(o + i);
+    }
+}
+
+// For every group g of the segments:
+//   part[(g * gridDim.x + blk) * nout + l0 + u] = sum over the block's entries
+//   of group g of X_u[i] w[i] (u < NV), and if self the same at l0 + NV for
+//   sum w[i]^2.
 template <int NV, bool V2>
 __global__ void __launch_bounds__(kBlock) dots_kernel(const double* __restrict__ X, long long ld,
-                                                      const double* __restrict__ w, long long n, int self,
+                                                      const double* __restrict__ w, Segs sg, int self,
                                                       double* __restrict__ part, int nout, int l0) {
     __shared__ double sh[kBlock / 64];
     constexpr int NA = NV > 0 ? NV : 1;
-    double acc[NA], accs = 0.0;
-#pragma unroll
-    for (int u = 0; u < NA; ++u) acc[u] = 0.0;
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long step = (long long)gridDim.x * blockDim.x;
-    if constexpr (V2) {
-        const long long n2 = n >> 1;
-        for (long long i = tid; i < n2; i += step) {
-            const double2 wi = reinterpret_cast<const double2*>(w)[i];
+    for (int g = 0; g < sg.ngroup; ++g) {
+        double acc[NA], accs = 0.0;
+#pragma unroll
+        for (int u = 0; u < NA; ++u) acc[u] = 0.0;
+        auto pair = [&](long long i) {
+            const double2 wi = *reinterpret_cast<const double2*>(w + i);
             double2 xv[NA];
 #pragma unroll
-            for (int u = 0; u < NV; ++u) xv[u] = reinterpret_cast<const double2*>(X + u * ld)[i];
+            for (int u = 0; u < NV; ++u) xv[u] = *reinterpret_cast<const double2*>(X + u * ld + i);
 #pragma unroll
             for (int u = 0; u < NV; ++u) acc[u] = fma(xv[u].y, wi.y, fma(xv[u].x, wi.x, acc[u]));
             accs = fma(wi.y, wi.y, fma(wi.x, wi.x, accs));
-        }
-        if ((n & 1) && tid == 0) {
-            const double wi = w[n - 1];
-#pragma unroll
-            for (int u = 0; u < NV; ++u) acc[u] = fma(X[u * ld + n - 1], wi, acc[u]);
-            accs = fma(wi, wi, accs);
-        }
-    } else {
-        for (long long i = tid; i < n; i += step) {
+        };
+        auto one = [&](long long i) {
             const double wi = w[i];
             double xv[NA];
 #pragma unroll
@@ -264,58 +281,53 @@ __global__ void __launch_bounds__(kBlock) dots_kernel(const double* __restrict__
 #pragma unroll
             for (int u = 0; u < NV; ++u) acc[u] = fma(xv[u], wi, acc[u]);
             accs = fma(wi, wi, accs);
-        }
-    }
+        };
+        for (int q = sg.first[g]; q < sg.first[g + 1]; ++q) seg_loop<V2>(sg.off[q], sg.len[q], tid, step, pair, one);
+        double* pg = part + ((long long)g * gridDim.x + blockIdx.x) * nout + l0;
 #pragma unroll
-    for (int u = 0; u < NV; ++u) {
-        const double t = block_sum(acc[u], sh);
-        if (threadIdx.x == 0) part[(long long)blockIdx.x * nout + l0 + u] = t;
-    }
-    if (self) {
-        const double t = block_sum(accs, sh);
-        if (threadIdx.x == 0) part[(long long)blockIdx.x * nout + l0 + NV] = t;
+        for (int u = 0; u < NV; ++u) {
+            const double t = block_sum(acc[u], sh);
+            if (threadIdx.x == 0) pg[u] = t;
+        }
+        if (self) {
+            const double t = block_sum(accs, sh);
+            if (threadIdx.x == 0) pg[NV] = t;
+        }
     }
 }
 
-// out = src - sum_u h[u] sig[u] X_u (sig may be null; out may alias src);
-// if norm_part: norm_part[blk] = sum of out^2 over the block's entries.
+// Per group g: out = src - sum_u h[g hstride + u] sig[u kSigStride + g] X_u
+// over the group's segments (sig may be null; out may alias src); if
+// norm_part: norm_part[g gridDim.x + blk] = sum of out^2 over the block's
+// entries of the group.
 template <int NV, bool V2>
 __global__ void __launch_bounds__(kBlock) gs_update_kernel(const double* __restrict__ X, long long ld,
-                                                           const double* __restrict__ h,
+                                                           const double* __restrict__ h, int hstride,
                                                            const double* __restrict__ sig,
-                                                           const double* src, double* out, long long n,
+                                                           const double* src, double* out, Segs sg,
                                                            double* __restrict__ norm_part) {
     __shared__ double sh[kBlock / 64];
-    double coef[NV];
-#pragma unroll
-    for (int u = 0; u < NV; ++u) coef[u] = -h[u] * (sig ? sig[u] : 1.0);
-    double nrm = 0.0;
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long step = (long long)gridDim.x * blockDim.x;
-    if constexpr (V2) {
-        const long long n2 = n >> 1;
-        for (long long i = tid; i < n2; i += step) {
-            double2 acc = reinterpret_cast<const double2*>(src)[i];
+    for (int g = 0; g < sg.ngroup; ++g) {
+        double coef[NV];
+#pragma unroll
+        for (int u = 0; u < NV; ++u) coef[u] = -h[g * hstride + u] * (sig ? sig[u * kSigStride + g] : 1.0);
+        double nrm = 0.0;
+        auto pair = [&](long long i) {
+            double2 acc = *reinterpret_cast<const double2*>(src + i);
             double2 xv[NV];
 #pragma unroll
-            for (int u = 0; u < NV; ++u) xv[u] = reinterpret_cast<const double2*>(X + u * ld)[i];
+            for (int u = 0; u < NV; ++u) xv[u] = *reinterpret_cast<const double2*>(X + u * ld + i);
 #pragma unroll
             for (int u = 0; u < NV; ++u) {
                 acc.x = fma(coef[u], xv[u].x, acc.x);
                 acc.y = fma(coef[u], xv[u].y, acc.y);
             }
-            reinterpret_cast<double2*>(out)[i] = acc;
+            *reinterpret_cast<double2*>(out + i) = acc;
             nrm = fma(acc.y, acc.y, fma(acc.x, acc.x, nrm));
-        }
-        if ((n & 1) && tid == 0) {
-            double acc = src[n - 1];
-#pragma unroll
-            for (int u = 0; u < NV; ++u) acc = fma(coef[u], X[u * ld + n - 1], acc);
-            out[n - 1] = acc;
-            nrm = fma(acc, acc, nrm);
-        }
-    } else {
-        for (long long i = tid; i < n; i += step) {
+        };
+        auto one = [&](long long i) {
             double acc = src[i];
             double xv[NV];
 #pragma unroll
@@ -324,68 +336,67 @@ __global__ void __launch_bounds__(kBlock) gs_update_kernel(const double* __restr
             for (int u = 0; u < NV; ++u) acc = fma(coef[u], xv[u], acc);
             out[i] = acc;
             nrm = fma(acc, acc, nrm);
+        };
+        for (int q = sg.first[g]; q < sg.first[g + 1]; ++q) seg_loop<V2>(sg.off[q], sg.len[q], tid, step, pair, one);
+        if (norm_part) {
+            const double t = block_sum(nrm, sh);
+            if (threadIdx.x == 0) norm_part[(long long)g * gridDim.x + blockIdx.x] = t;
         }
     }
-    if (norm_part) {
-        const double t = block_sum(nrm, sh);
-        if (threadIdx.x == 0) norm_part[blockIdx.x] = t;
-    }
 }
 
+// Block (l, g): out[g ostride + l] (+)= scale[l kSigStride + g] * sum_b
+// part[(g nblocks + b) nout + l]; for l = nout - 1 also inv_sqrt_out[g].
 __global__ void reduce_kernel(const double* __restrict__ part, int nblocks, int nout,
-                              double* __restrict__ out, int accumulate, const double* __restrict__ scale,
-                              int nscale, double* __restrict__ inv_sqrt_out) {
+                              double* __restrict__ out, int ostride, int accumulate,
+                              const double* __restrict__ scale, int nscale, double* __restrict__ inv_sqrt_out) {
     __shared__ double sh[kBlock / 64];
-    const int l = blockIdx.x;
+    const int l = blockIdx.x, g = blockIdx.y;
+    const double* pg = part + (long long)g * nblocks * nout;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += part[(long long)b * nout + l];
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += pg[(long long)b * nout + l];
     double t = block_sum(acc, sh);
     if (threadIdx.x == 0) {
-        if (scale && l < nscale) t *= scale[l];
-        out[l] = accumulate ? out[l] + t : t;
-        if (inv_sqrt_out && l == nout - 1) *inv_sqrt_out = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+        if (scale && l < nscale) t *= scale[l * kSigStride + g];
+        double* o = out + (long long)g * ostride + l;
+        *o = accumulate ? *o + t : t;
+        if (inv_sqrt_out && l == nout - 1) inv_sqrt_out[g] = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
     }
 }
 
 
-// kv += sum_u y[u] Z_u for a chunk of NV vectors (Z fp64 or fp32)
+// kv += sum_u y[g ystride + u] Z_u over the segments of every group g, for
+// a chunk of NV vectors (Z fp64 or fp32)
 template <int NV, typename TZ, bool V2>
 __global__ void __launch_bounds__(kBlock) combine_kernel(double* __restrict__ kv, const TZ* __restrict__ Z,
                                                          long long ld, const double* __restrict__ y,
-                                                         long long n) {
-    double coef[NV];
-#pragma unroll
-    for (int u = 0; u < NV; ++u) coef[u] = y[u];
+                                                         int ystride, Segs sg) {
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long step = (long long)gridDim.x * blockDim.x;
-    if constexpr (V2) {
-        using P2 = typename Pair<TZ>::type;
-        const long long n2 = n >> 1;
-        for (long long i = tid; i < n2; i += step) {
-            double2 acc = reinterpret_cast<const double2*>(kv)[i];
+    for (int g = 0; g < sg.ngroup; ++g) {
+        double coef[NV];
+#pragma unroll
+        for (int u = 0; u < NV; ++u) coef[u] = y[g * ystride + u];
+        auto pair = [&](long long i) {
+            using P2 = typename Pair<TZ>::type;
+            double2 acc = *reinterpret_cast<const double2*>(kv + i);
             P2 zv[NV];
 #pragma unroll
-            for (int u = 0; u < NV; ++u) zv[u] = reinterpret_cast<const P2*>(Z + u * ld)[i];
+            for (int u = 0; u < NV; ++u) zv[u] = *reinterpret_cast<const P2*>(Z + u * ld + i);
 #pragma unroll
             for (int u = 0; u < NV; ++u) {
                 acc.x = fma(coef[u], (double)zv[u].x, acc.x);
                 acc.y = fma(coef[u], (double)zv[u].y, acc.y);
             }
-            reinterpret_cast<double2*>(kv)[i] = acc;
-        }
-        if ((n & 1) && tid == 0) {
-            double acc = kv[n - 1];
-#pragma unroll
-            for (int u = 0; u < NV; ++u) acc = fma(coef[u], (double)Z[u * ld + n - 1], acc);
-            kv[n - 1] = acc;
-        }
-    } else {
-        for (long long i = tid; i < n; i += step) {
+            *reinterpret_cast<double2*>(kv + i) = acc;
+        };
+        auto one = [&](long long i) {
             double acc = kv[i];
 #pragma unroll
             for (int u = 0; u < NV; ++u) acc = fma(coef[u], (double)Z[u * ld + i], acc);
             kv[i] = acc;
-        }
+        };
+        for (int q = sg.first[g]; q < sg.first[g + 1]; ++q) seg_loop<V2>(sg.off[q], sg.len[q], tid, step, pair, one);
     }
 }
 
@@ -523,17 +534,19 @@ hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* 
 
 hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* out, const double* D,
                             int qout, int qin, int N, hipStream_t st, double* out2, const double* D2,
-                            const double* in_scale) {
+                            const double* in_scale, const SlotIdx* scale_idx) {
     const long long N3 = (long long)N * N * N;
     dim3 g(grid_for(N3)), b(kBlock);
+    SlotIdx sidx;
+    for (int j = 0; j < RK_MAX_Q; ++j) sidx.v[j] = scale_idx ? scale_idx->v[j] : 0;
     if (dtype_in == RK_FP64 && dtype_out == RK_FP64)
-        stage_mix_kernel<double, double><<<g, b, 0, st>>>((const double*)in, (double*)out, D, qout, qin, N, out2, D2, in_scale);
+        stage_mix_kernel<double, double><<<g, b, 0, st>>>((const double*)in, (double*)out, D, qout, qin, N, out2, D2, in_scale, sidx);
     else if (dtype_in == RK_FP64 && dtype_out == RK_FP32)
-        stage_mix_kernel<double, float><<<g, b, 0, st>>>((const double*)in, (float*)out, D, qout, qin, N, out2, D2, in_scale);
+        stage_mix_kernel<double, float><<<g, b, 0, st>>>((const double*)in, (float*)out, D, qout, qin, N, out2, D2, in_scale, sidx);
     else if (dtype_in == RK_FP32 && dtype_out == RK_FP64)
-        stage_mix_kernel<float, double><<<g, b, 0, st>>>((const float*)in, (double*)out, D, qout, qin, N, out2, D2, in_scale);
+        stage_mix_kernel<float, double><<<g, b, 0, st>>>((const float*)in, (double*)out, D, qout, qin, N, out2, D2, in_scale, sidx);
     else
-        stage_mix_kernel<float, float><<<g, b, 0, st>>>((const float*)in, (float*)out, D, qout, qin, N, out2, D2, in_scale);
+        stage_mix_kernel<float, float><<<g, b, 0, st>>>((const float*)in, (float*)out, D, qout, qin, N, out2, D2, in_scale, sidx);
     return hipGetLastError();
 }
 
@@ -546,13 +559,15 @@ hipError_t launch_rhs_mix(const double* G, const double* w, double* out, const d
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w, long long n, int self,
+// V2 paths need 16-byte aligned vector bases and an even leading dimension;
+// segments at odd offsets are handled element-wise at their ends.
+hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w, const Segs& sg, int self,
                        double* part, int nblocks, hipStream_t st) {
     const int nout = nvec + self;
     const bool v2 = aligned16(w) && (nvec == 0 || (aligned16(X) && ld % 2 == 0));
     if (nvec == 0) {
-        if (v2) dots_kernel<0, true><<<nblocks, kBlock, 0, st>>>(X, ld, w, n, self, part, nout, 0);
-        else dots_kernel<0, false><<<nblocks, kBlock, 0, st>>>(X, ld, w, n, self, part, nout, 0);
+        if (v2) dots_kernel<0, true><<<nblocks, kBlock, 0, st>>>(X, ld, w, sg, self, part, nout, 0);
+        else dots_kernel<0, false><<<nblocks, kBlock, 0, st>>>(X, ld, w, sg, self, part, nout, 0);
         return hipGetLastError();
     }
     for (int l0 = 0; l0 < nvec; l0 += kChunk) {
@@ -560,8 +575,8 @@ hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w,
         const int sf = (self && l0 + nv == nvec) ? 1 : 0;
         const double* Xc = X + (long long)l0 * ld;
         hipError_t e = dispatch_nv(nv, [&](auto NV) {
-            if (v2) dots_kernel<NV, true><<<nblocks, kBlock, 0, st>>>(Xc, ld, w, n, sf, part, nout, l0);
-            else dots_kernel<NV, false><<<nblocks, kBlock, 0, st>>>(Xc, ld, w, n, sf, part, nout, l0);
+            if (v2) dots_kernel<NV, true><<<nblocks, kBlock, 0, st>>>(Xc, ld, w, sg, sf, part, nout, l0);
+            else dots_kernel<NV, false><<<nblocks, kBlock, 0, st>>>(Xc, ld, w, sg, sf, part, nout, l0);
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;
@@ -569,9 +584,9 @@ hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w,
     return hipSuccess;
 }
 
-hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, const double* sig,
-                            const double* w, double* out, long long n, double* norm_part, int nblocks,
-                            hipStream_t st) {
+hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, int hstride,
+                            const double* sig, const double* w, double* out, const Segs& sg, double* norm_part,
+                            int nblocks, hipStream_t st) {
     const bool v2 = aligned16(X) && aligned16(w) && aligned16(out) && ld % 2 == 0;
     if (nvec <= 0) return hipErrorInvalidValue;
     for (int l0 = 0; l0 < nvec; l0 += kChunk) {
@@ -579,11 +594,13 @@ hipError_t launch_gs_update(const double* X, int nvec, long long ld, const doubl
         const bool last = l0 + nv == nvec;
         const double* Xc = X + (long long)l0 * ld;
         const double* src = l0 == 0 ? w : out;
-        const double* sc = sig ? sig + l0 : nullptr;
+        const double* sc = sig ? sig + (long long)l0 * kSigStride : nullptr;
         double* np = last ? norm_part : nullptr;
         hipError_t e = dispatch_nv(nv, [&](auto NV) {
-            if (v2) gs_update_kernel<NV, true><<<nblocks, kBlock, 0, st>>>(Xc, ld, h + l0, sc, src, out, n, np);
-            else gs_update_kernel<NV, false><<<nblocks, kBlock, 0, st>>>(Xc, ld, h + l0, sc, src, out, n, np);
+            if (v2)
+                gs_update_kernel<NV, true><<<nblocks, kBlock, 0, st>>>(Xc, ld, h + l0, hstride, sc, src, out, sg, np);
+            else
+                gs_update_kernel<NV, false><<<nblocks, kBlock, 0, st>>>(Xc, ld, h + l0, hstride, sc, src, out, sg, np);
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;
@@ -592,16 +609,19 @@ hipError_t launch_gs_update(const double* X, int nvec, long long ld, const doubl
 }
 
 hipError_t launch_reduce(const double* part, int nblocks, int nout, double* out, int accumulate,
-                         hipStream_t st, const double* scale, int nscale, double* inv_sqrt_out) {
-    reduce_kernel<<<nout, kBlock, 0, st>>>(part, nblocks, nout, out, accumulate, scale, nscale, inv_sqrt_out);
+                         hipStream_t st, const double* scale, int nscale, double* inv_sqrt_out, int ngroup,
+                         int ostride) {
+    reduce_kernel<<<dim3(nout, ngroup), kBlock, 0, st>>>(part, nblocks, nout, out, ostride, accumulate, scale,
+                                                         nscale, inv_sqrt_out);
     return hipGetLastError();
 }
 
-
 hipError_t launch_combine(double* kv, int dtype_z, const void* Z, int nz, long long ld, const double* y,
-                          long long n, hipStream_t st) {
+                          int ystride, const Segs& sg, hipStream_t st) {
     const size_t es = dtype_z == RK_FP64 ? 8 : 4;
     const bool v2 = aligned16(kv) && (reinterpret_cast<uintptr_t>(Z) % (2 * es)) == 0 && ld % 2 == 0;
+    long long n = 0;
+    for (int q = 0; q < sg.first[sg.ngroup]; ++q) n += sg.len[q];
     const int nb = grid_for(n / 2 + 1);
     for (int l0 = 0; l0 < nz; l0 += kChunk) {
         const int nv = std::min(kChunk, nz - l0);
@@ -609,12 +629,12 @@ hipError_t launch_combine(double* kv, int dtype_z, const void* Z, int nz, long l
         hipError_t e = dispatch_nv(nv, [&](auto NV) {
             if (dtype_z == RK_FP64) {
                 const double* z = reinterpret_cast<const double*>(Zc);
-                if (v2) combine_kernel<NV, double, true><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, n);
-                else combine_kernel<NV, double, false><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, n);
+                if (v2) combine_kernel<NV, double, true><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, ystride, sg);
+                else combine_kernel<NV, double, false><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, ystride, sg);
             } else {
                 const float* z = reinterpret_cast<const float*>(Zc);
-                if (v2) combine_kernel<NV, float, true><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, n);
-                else combine_kernel<NV, float, false><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, n);
+                if (v2) combine_kernel<NV, float, true><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, ystride, sg);
+                else combine_kernel<NV, float, false><<<nb, kBlock, 0, st>>>(kv, z, ld, y + l0, ystride, sg);
             }
             return hipGetLastError();
         });

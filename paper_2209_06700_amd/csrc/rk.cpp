@@ -46,15 +46,18 @@ namespace {
 constexpr int kRedBlocks = 2048;     // blocks of the reduction kernels
 // slots (x 81 doubles) of the device Q x Q mixing data
 constexpr int kMixSinv = 0, kMixS = 81, kMixRhs = 162, kMixAinvS = 243, kMixAinv = 324, kMixA = 405;
+// direct diagonalisation: Lam_r, PRESB input and output mixes, Lam_r times the output mix
+constexpr int kMixCLam = 486, kMixPin = 567, kMixPout = 648, kMixLamPout = 729, kMixSlots = 10;
 constexpr size_t kAlign = 256;
 
-enum Form { F_CALA = 0, F_STAGE = 1, F_BLOCKS = 2, F_K = 3, F_M = 4, F_NFORMS = 5 };
+enum Form { F_CALA = 0, F_STAGE = 1, F_BLOCKS = 2, F_K = 3, F_M = 4, F_CBLK = 5, F_NFORMS = 6 };
 
 // Mixing coefficients of one operator form (cell size folded in).
 struct Coeffs {
     double alpha[RK_MAX_Q] = {}, beta[RK_MAX_Q] = {};
     bool pair = false;      // two inputs: mass-term input, stiffness-term input
-    int premix = 0;         // pair forms: 1 = mass input is (A^-1 (x) I) u, 2 = stiffness input is (A (x) I) u
+    int premix = 0;         // pair forms: 1 = mass input is (A^-1 (x) I) u, 2 = stiffness input is
+                            // (A (x) I) u, 3 = mass input is (Lam_r (x) I) u
 };
 
 struct Level {
@@ -108,8 +111,14 @@ struct rk_ctx {
     hipGraphExec_t vc_exec = nullptr;
     int vc_graph = 0;              // 0 not tried, 1 captured, -1 eager only
     int pc = RK_FP64;              // preconditioner dtype
+    bool cplx = false;             // direct diagonalisation with PRESB
+    int ng = 1;                    // independent Krylov systems (complex: the nb blocks)
+    Segs seg;                      // their segments of the Krylov vectors
+    SlotIdx slot_group;            // slot -> group
+    int nscal = 0;                 // per-group stride of scal / scal2 / ycoef
     std::vector<Level> lv;
     Coeffs form[F_NFORMS];         // fine-level operator coefficients
+    Coeffs presb_m;                // PRESB coupling: Im(lam_j) M on slots nb + j
     void* tmp = nullptr;           // restriction intermediate
     long long ld = 0;              // stride of the Krylov vectors (Q N3 padded to 256 bytes)
     double* V = nullptr;           // (restart+1) x ld
@@ -118,12 +127,12 @@ struct rk_ctx {
     double* kv = nullptr;          // Q N3
     double* rhs = nullptr;         // Q N3
     double* Ky = nullptr;          // N3
-    double* part = nullptr;        // kRedBlocks x (restart + 8)
-    double* scal = nullptr;        // restart + 16 device scalars
-    double* scal2 = nullptr;       // restart + 16
-    double* ycoef = nullptr;       // restart
-    double* sig = nullptr;         // restart + 2: 1 / ||Vhat_i|| of the Krylov basis
-    double* mix = nullptr;         // 8 x 81: Sinv, S, rhs coefficients, Ainv S, Ainv, A
+    double* part = nullptr;        // groups x kRedBlocks x nscal
+    double* scal = nullptr;        // groups x nscal device scalars
+    double* scal2 = nullptr;       // groups x nscal
+    double* ycoef = nullptr;       // groups x nscal
+    double* sig = nullptr;         // (restart + 16) x kSigStride: 1 / ||Vhat_i|| per group
+    double* mix = nullptr;         // kMixSlots x 81: the Q x Q mixing matrices
     void* mbuf = nullptr;          // Q N3 (fp64-sized): mixed input of the pair operators
     std::vector<double> host_scal;
     std::vector<Event> events;
@@ -161,6 +170,7 @@ bool valid_options(const rk_options& o, std::string& msg) {
         msg = "bad Chebyshev degree"; return false;
     }
     if (!(o.cheb_range > 1.0) || !(o.eig_safety > 0.0) || o.eig_iterations < 1) { msg = "bad Chebyshev interval settings"; return false; }
+    if (o.method != RK_METHOD_CROUT && o.method != RK_METHOD_COMPLEX) { msg = "bad method"; return false; }
     return true;
 }
 
@@ -171,18 +181,24 @@ bool valid_options(const rk_options& o, std::string& msg) {
 // kernel, then the pair operator runs on (mixed input, plain input))
 //   BLOCKS: v_s = lam_s h^3 Mref u_s + tau h Kref u_s              (eq. irk:P blocks)
 //   K, M:   one vector.
+//   CBLK:   v_s = h^3 Mref (sum_j Lam_r,sj u_j) + tau h Kref u_s   (Sec. 6 blocks)
+// The multigrid blocks of a level are lam_i M + tau K (eq. irk:P), or for the
+// complex method the PRESB matrices H = (Re lam + Im lam) M + tau K per slot.
 Coeffs make_coeffs(const rk_ctx& c, double h, int form) {
     const int Q = c.Q;
     Coeffs r;
     const double h3 = h * h * h;
     for (int s = 0; s < RK_MAX_Q; ++s) {
-        if (form == F_BLOCKS && s < Q) { r.alpha[s] = c.tab.lam[s] * h3; r.beta[s] = c.tau * h; }
+        if (form == F_BLOCKS && s < Q) {
+            r.alpha[s] = (c.cplx ? c.tab.hshift[s] : c.tab.lam[s]) * h3;
+            r.beta[s] = c.tau * h;
+        }
         if (form == F_K) { r.alpha[s] = 0.0; r.beta[s] = h; }
         if (form == F_M) { r.alpha[s] = h3; r.beta[s] = 0.0; }
     }
-    if (form == F_CALA || form == F_STAGE) {
+    if (form == F_CALA || form == F_STAGE || form == F_CBLK) {
         r.pair = true;
-        r.premix = form == F_CALA ? 1 : 2;
+        r.premix = form == F_CALA ? 1 : form == F_STAGE ? 2 : 3;
         for (int q = 0; q < Q; ++q) { r.alpha[q] = h3; r.beta[q] = c.tau * h; }
     }
     return r;
@@ -221,12 +237,14 @@ size_t carve(rk_ctx& c, char* base) {
     c.rhs = (double*)cv.take(8 * qn);
     c.Ky = (double*)cv.take(8 * c.N3);
     const size_t nscal = std::max(m + 16, 3 * RK_MAX_Q + 1);
-    c.part = (double*)cv.take(8 * (size_t)kRedBlocks * nscal);
-    c.scal = (double*)cv.take(8 * nscal);
-    c.scal2 = (double*)cv.take(8 * nscal);
-    c.ycoef = (double*)cv.take(8 * (size_t)(m + 16));
-    c.sig = (double*)cv.take(8 * (size_t)(m + 16));
-    c.mix = (double*)cv.take(8 * 8 * 81);
+    const size_t ngmax = (size_t)(Q + 1) / 2;
+    c.nscal = (int)nscal;
+    c.part = (double*)cv.take(8 * (size_t)kRedBlocks * nscal * ngmax);
+    c.scal = (double*)cv.take(8 * nscal * ngmax);
+    c.scal2 = (double*)cv.take(8 * nscal * ngmax);
+    c.ycoef = (double*)cv.take(8 * nscal * ngmax);
+    c.sig = (double*)cv.take(8 * (size_t)(m + 16) * kSigStride);
+    c.mix = (double*)cv.take(8 * kMixSlots * 81);
     c.mbuf = cv.take(8 * (size_t)qn);
     return cv.off + kAlign;
 }
@@ -250,6 +268,7 @@ int setup_sizes(rk_ctx& c, const rk_mesh* mesh, int degree, int Q, const rk_opti
     c.N3 = (long long)c.N * c.N * c.N;
     c.h = 1.0 / c.n;
     c.pc = c.opt.precision == RK_PREC_MIXED ? RK_FP32 : RK_FP64;
+    c.cplx = c.opt.method == RK_METHOD_COMPLEX;
     c.lv.clear();
     for (int m : level_cells(c.n)) {
         Level L;
@@ -420,43 +439,70 @@ int vcycle_level(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, v
     return RK_OK;
 }
 
-// V-cycles for all Q blocks on the finest level: b -> x (both [Q][N3]).
-int vcycle_all(rk_ctx* c, const void* b, void* x) {
-    Level& F = c->lv[0];
+// V-cycles for the blocks of slots [s0, s0+ns) on the finest level: b -> x
+// (stage-0 bases of [Q][N3] buffers), with `scratch` as the second iterate
+// buffer.  Batched: one launch sequence for the range; per-stage: slot by slot.
+int vcycle_range(rk_ctx* c, const void* b, void* x, void* scratch, int s0, int ns) {
     const bool single = c->lv.size() == 1;
     const bool res_first = single && (c->opt.coarse_cheb_degree % 2 == 1);
-    void* first = res_first ? x : F.y;
-    void* second = res_first ? F.y : x;
-    const int groups = c->opt.mode == RK_BATCHED ? 1 : c->Q;
-    const int ns = c->opt.mode == RK_BATCHED ? c->Q : 1;
+    void* first = res_first ? x : scratch;
+    void* second = res_first ? scratch : x;
+    const int groups = c->opt.mode == RK_BATCHED ? 1 : ns;
+    const int per = c->opt.mode == RK_BATCHED ? ns : 1;
     for (int g = 0; g < groups; ++g) {
         void* res = nullptr;
-        int rc = vcycle_level(c, 0, g * ns, ns, b, first, second, &res);
+        int rc = vcycle_level(c, 0, s0 + g * per, per, b, first, second, &res);
         if (rc) return rc;
         if (res != x) return fail(c, RK_EHIP, "internal: V-cycle result buffer");
     }
     return RK_OK;
 }
 
-// V-cycles F.b -> F.x for all blocks: replay of the captured graph, or eager
-// launches (timing mode, RK_NO_GRAPH set, or capture unavailable).
-int run_vcycle(rk_ctx* c) {
+// V-cycles for all Q blocks on the finest level: b -> x (both [Q][N3]).
+int vcycle_all(rk_ctx* c, const void* b, void* x) {
+    return vcycle_range(c, b, x, c->lv[0].y, 0, c->Q);
+}
+
+// The block solves of PRESB (eq. presb:p) on the fixed buffers, F.b -> F.x
+// in slots: g1 = V(H)(F.b) on slots [0, nb) (the pairs' r_re + r_im and the
+// real block), then f2 = F.b - Im(lam) M g1 on slots [nb, Q) into F.y, then
+// g2 = V(H)(f2) on slots [nb, Q) (F.b serves as scratch).
+int presb_blocks(rk_ctx* c) {
     Level& F = c->lv[0];
+    const int nb = c->tab.nb, np = c->tab.npair;
+    int rc = vcycle_range(c, F.b, F.x, F.y, 0, nb);
+    if (rc || np == 0) return rc;
+    // input slot j feeds output slot nb + j: shift the input base by -nb slots
+    const size_t es = dsize(c->pc);
+    const void* g1 = (const void*)((uintptr_t)F.x - (uintptr_t)(es * nb * F.N3));
+    rc = op(c, c->k, c->pc, EPI_RESID, c->presb_m, g1, F.y, F.b, nullptr, F.n, nb, np, 0, 0);
+    if (rc) return rc;
+    return vcycle_range(c, F.y, F.x, F.b, nb, np);
+}
+
+// The block solves of the preconditioner on F.b -> F.x.
+int blocks_eager(rk_ctx* c) {
+    return c->cplx ? presb_blocks(c) : vcycle_all(c, c->lv[0].b, c->lv[0].x);
+}
+
+// Block solves F.b -> F.x: replay of the captured graph, or eager launches
+// (timing mode, RK_NO_GRAPH set, or capture unavailable).
+int run_blocks(rk_ctx* c) {
     static const bool no_graph = std::getenv("RK_NO_GRAPH") != nullptr;   // A/B override
-    if (c->opt.timing || no_graph || c->vc_graph < 0) return vcycle_all(c, F.b, F.x);
+    if (c->opt.timing || no_graph || c->vc_graph < 0) return blocks_eager(c);
     if (c->vc_graph == 0) {
         c->vc_graph = -1;
         if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
             (void)hipGetLastError();
-            return vcycle_all(c, F.b, F.x);
+            return blocks_eager(c);
         }
         if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             (void)hipGetLastError();
-            return vcycle_all(c, F.b, F.x);
+            return blocks_eager(c);
         }
         hipStream_t user = c->stream;
         c->stream = c->cap_stream;
-        const int rc = vcycle_all(c, F.b, F.x);
+        const int rc = blocks_eager(c);
         c->stream = user;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -465,7 +511,7 @@ int run_vcycle(rk_ctx* c) {
         if (rc != RK_OK || e != hipSuccess || !c->vc_exec) {
             (void)hipGetLastError();
             c->vc_exec = nullptr;
-            return vcycle_all(c, F.b, F.x);
+            return blocks_eager(c);
         }
         c->vc_graph = 1;
     }
@@ -473,24 +519,30 @@ int run_vcycle(rk_ctx* c) {
     return RK_OK;
 }
 
-// z = P^-1 r (eq. irk:P); r, z fp64 [Q][N3].  If m is given, m = (A^-1 (x) I) z
-// is written in the same pass (the mass-term input of the operator of eq. irk:A).
+// z = P^-1 r on fp64 [Q][N3] vectors: eq. (irk:P) for the Crout method,
+// PRESB on slot vectors (eq. presb:p) for the complex method.  If m is given,
+// m = (A^-1 (x) I) z, respectively (Lam_r (x) I) z, is written in the same
+// pass (the mass-term input of the Krylov operator).  r_scale: per-group
+// scales of r (r_scale[group of slot j] multiplies slot j), or null.
 int precondition(rk_ctx* c, const double* r, double* z, double* m = nullptr,
                  const double* r_scale = nullptr) {
     Level& F = c->lv[0];
+    const int in = c->cplx ? kMixPin : kMixSinv;
+    const int out = c->cplx ? kMixPout : kMixS;
+    const int out2 = c->cplx ? kMixLamPout : kMixAinvS;
     {
         Timer t(c, C_BASIS);
-        HIPCHK(c, launch_stage_mix(RK_FP64, r, c->pc, F.b, c->mix + kMixSinv, c->Q, c->Q, c->N, c->stream,
-                                   nullptr, nullptr, r_scale));
+        HIPCHK(c, launch_stage_mix(RK_FP64, r, c->pc, F.b, c->mix + in, c->Q, c->Q, c->N, c->stream,
+                                   nullptr, nullptr, r_scale, &c->slot_group));
     }
     {
         Timer t(c, C_BLOCKS);
-        int rc = run_vcycle(c);
+        int rc = run_blocks(c);
         if (rc) return rc;
     }
     Timer t(c, C_BASIS);
-    HIPCHK(c, launch_stage_mix(c->pc, F.x, RK_FP64, z, c->mix + kMixS, c->Q, c->Q, c->N, c->stream, m,
-                               m ? c->mix + kMixAinvS : nullptr));
+    HIPCHK(c, launch_stage_mix(c->pc, F.x, RK_FP64, z, c->mix + out, c->Q, c->Q, c->N, c->stream, m,
+                               m ? c->mix + out2 : nullptr));
     return RK_OK;
 }
 
@@ -521,58 +573,207 @@ int estimate_eigs(rk_ctx* c) {
     return RK_OK;
 }
 
-// Arnoldi step j.  The basis is stored unnormalised, V_i = sig[i] Vhat_i with
-// the scale factors sig on the device, so no separate normalisation pass is
-// needed.  w = A z_j is orthogonalised against V_0..V_j by classical
-// Gram-Schmidt (one fused dot pass and one update pass); a second pass runs
-// only when the projection cancelled all but 1e-4 of ||w||^2.  The result
-// goes to Vhat_{j+1} and sig[j+1] = 1/||Vhat_{j+1}||.  Returns h[0..j] and
-// h[j+1] = ||w_orth|| on the host.
+// Arnoldi step j for every group (independent system) at once.  The basis is
+// stored unnormalised, V_i = sig[i][g] Vhat_i on group g, with the scale
+// factors sig on the device, so no separate normalisation pass is needed.
+// w = A z_j is orthogonalised against V_0..V_j by classical Gram-Schmidt
+// (one fused dot pass and one update pass); a second pass runs when in some
+// group the projection cancelled all but 1e-4 of ||w||^2.  The result goes to
+// Vhat_{j+1} and sig[j+1][g] = 1/||Vhat_{j+1}|| on g.  Returns, per group g,
+// hcol[g * (restart + 2) + i] = h_ij (i <= j) and h_{j+1,j} = ||w_orth||.
 int arnoldi_orth(rk_ctx* c, int j, double* hcol) {
-    const long long qn = (long long)c->Q * c->N3;
-    const int nv = j + 1;
+    const int nv = j + 1, ng = c->ng, NS = c->nscal, hs = c->opt.restart + 2;
     double* Vn = c->V + (long long)nv * c->ld;
-    double* hs = c->host_scal.data();
-    HIPCHK(c, launch_dots(c->V, nv, c->ld, c->w, qn, 1, c->part, kRedBlocks, c->stream));
-    HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv + 1, c->scal, 0, c->stream, c->sig, nv));
-    HIPCHK(c, launch_gs_update(c->V, nv, c->ld, c->scal, c->sig, c->w, Vn, qn, c->part, kRedBlocks, c->stream));
-    HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream, nullptr, 0, c->sig + nv));
-    HIPCHK(c, hipMemcpyAsync(hs, c->scal, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, c->stream));
+    double* host = c->host_scal.data();
+    double* sig_n = c->sig + (long long)nv * kSigStride;
+    HIPCHK(c, launch_dots(c->V, nv, c->ld, c->w, c->seg, 1, c->part, kRedBlocks, c->stream));
+    HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv + 1, c->scal, 0, c->stream, c->sig, nv, nullptr, ng, NS));
+    HIPCHK(c, launch_gs_update(c->V, nv, c->ld, c->scal, NS, c->sig, c->w, Vn, c->seg, c->part, kRedBlocks,
+                               c->stream));
+    HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream, nullptr, 0, sig_n, ng, NS));
+    HIPCHK(c, hipMemcpyAsync(host, c->scal, sizeof(double) * NS * ng, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int i = 0; i < nv; ++i) hcol[i] = hs[i];
-    const double w2 = hs[nv];
-    double nrm2 = hs[nv + 1];
-    if (nrm2 < 1e-4 * w2) {
-        HIPCHK(c, launch_dots(c->V, nv, c->ld, Vn, qn, 0, c->part, kRedBlocks, c->stream));
-        HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv, c->scal2, 0, c->stream, c->sig, nv));
-        HIPCHK(c, launch_gs_update(c->V, nv, c->ld, c->scal2, c->sig, Vn, Vn, qn, c->part, kRedBlocks, c->stream));
-        HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal + nv + 1, 0, c->stream, nullptr, 0, c->sig + nv));
-        HIPCHK(c, hipMemcpyAsync(hs, c->scal2, sizeof(double) * nv, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemcpyAsync(hs + nv + 1, c->scal + nv + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        for (int i = 0; i < nv; ++i) hcol[i] += hs[i];
-        nrm2 = hs[nv + 1];
+    bool again = false;
+    for (int g = 0; g < ng; ++g) {
+        const double* hg = host + (long long)g * NS;
+        for (int i = 0; i < nv; ++i) hcol[g * hs + i] = hg[i];
+        hcol[g * hs + nv] = hg[nv + 1];          // ||w_orth||^2 for now
+        if (hg[nv + 1] < 1e-4 * hg[nv]) again = true;
     }
-    hcol[nv] = std::sqrt(std::max(nrm2, 0.0));
+    if (again) {
+        HIPCHK(c, launch_dots(c->V, nv, c->ld, Vn, c->seg, 0, c->part, kRedBlocks, c->stream));
+        HIPCHK(c, launch_reduce(c->part, kRedBlocks, nv, c->scal2, 0, c->stream, c->sig, nv, nullptr, ng, NS));
+        HIPCHK(c, launch_gs_update(c->V, nv, c->ld, c->scal2, NS, c->sig, Vn, Vn, c->seg, c->part, kRedBlocks,
+                                   c->stream));
+        HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal2 + nv, 0, c->stream, nullptr, 0, sig_n, ng, NS));
+        HIPCHK(c, hipMemcpyAsync(host, c->scal2, sizeof(double) * NS * ng, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int g = 0; g < ng; ++g) {
+            const double* hg = host + (long long)g * NS;
+            for (int i = 0; i < nv; ++i) hcol[g * hs + i] += hg[i];
+            hcol[g * hs + nv] = hg[nv];
+        }
+    }
+    for (int g = 0; g < ng; ++g) hcol[g * hs + nv] = std::sqrt(std::max(hcol[g * hs + nv], 0.0));
     return RK_OK;
 }
 
-// ||x||^2 on the host; with inv_sqrt, also 1/||x|| into that device scalar.
-double device_norm2(rk_ctx* c, const double* x, long long n, int* rc, double* inv_sqrt = nullptr) {
-    hipError_t e = launch_dots(nullptr, 0, 0, x, n, 1, c->part, kRedBlocks, c->stream);
-    if (e == hipSuccess) e = launch_reduce(c->part, kRedBlocks, 1, c->scal, 0, c->stream, nullptr, 0, inv_sqrt);
-    double v = 0.0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&v, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    *rc = e == hipSuccess ? RK_OK : fail(c, RK_EHIP, std::string("norm: ") + hipGetErrorString(e));
-    return v;
+// ||x||^2 per group on the host (out[g]); with inv_sqrt, also 1/||x|| per
+// group into those device scalars (inv_sqrt[g]).
+int group_norm2(rk_ctx* c, const double* x, double* out, double* inv_sqrt = nullptr) {
+    HIPCHK(c, launch_dots(nullptr, 0, 0, x, c->seg, 1, c->part, kRedBlocks, c->stream));
+    HIPCHK(c, launch_reduce(c->part, kRedBlocks, 1, c->scal, 0, c->stream, nullptr, 0, inv_sqrt, c->ng, c->nscal));
+    double* host = c->host_scal.data();
+    HIPCHK(c, hipMemcpyAsync(host, c->scal, sizeof(double) * c->nscal * c->ng, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int g = 0; g < c->ng; ++g) out[g] = host[(long long)g * c->nscal];
+    return RK_OK;
 }
 
-// v = (A^-1 (x) M + tau I (x) K) u given m = (A^-1 (x) I) u; with b, v = b - (...) u.
-int apply_cala(rk_ctx* c, const double* u, const double* m, double* v, const double* b) {
+// v = (D (x) M + tau I (x) K) u given m = (D (x) I) u, where D = A^-1 (eq.
+// irk:A, Crout method) or Lam_r (complex method); with b, v = b - (...) u.
+int apply_krylov(rk_ctx* c, const double* u, const double* m, double* v, const double* b) {
     Timer t(c, C_VMULT);
-    return op(c, c->k, RK_FP64, b ? EPI_RESID : EPI_STORE, c->form[F_CALA], m, v, b, nullptr, c->n, 0,
-              c->Q, 0, 0, u);
+    return op(c, c->k, RK_FP64, b ? EPI_RESID : EPI_STORE, c->form[c->cplx ? F_CBLK : F_CALA], m, v, b, nullptr,
+              c->n, 0, c->Q, 0, 0, u);
+}
+
+// Right-preconditioned flexible GMRES (Saad, Alg. 9.6; zero initial guess,
+// restarts of length m, Givens rotations) on c->ng independent systems in
+// lock step: the Krylov operator is block diagonal over the groups, every
+// group has its own basis scales, Hessenberg matrix, rotations and
+// convergence test ||r_g|| <= rtol ||rhs_g||, and all groups share every
+// kernel launch.  A group that has converged within a cycle keeps running
+// (its extra columns are not used); at a restart its start vector is scaled
+// to zero, so it contributes nothing further.  rhs: c->rhs; solution: c->kv.
+int gmres(rk_ctx* c, rk_stats& st, bool& converged) {
+    const int ng = c->ng, m = c->opt.restart, hs = m + 2;
+    const long long qn = (long long)c->Q * c->N3;
+    std::vector<double> bn(ng), rn(ng), sig0(ng);
+    int rc = group_norm2(c, c->rhs, bn.data());
+    if (rc) return rc;
+    for (auto& v : bn) v = std::sqrt(v);
+    HIPCHK(c, launch_fill(RK_FP64, c->kv, qn, 0.0, c->stream));
+    // the residual of each restart cycle lives in Vhat_0 (k_0 = 0: r = rhs)
+    HIPCHK(c, launch_copy(RK_FP64, c->rhs, c->V, qn, c->stream));
+    const int vc_per_it = c->opt.mode == RK_BATCHED ? (c->cplx && c->tab.npair > 0 ? 2 : 1) : c->Q;
+    std::vector<char> active(ng), done(ng);
+    std::vector<int> jd(ng);
+    std::vector<double> H((size_t)ng * (m + 1) * m), cs((size_t)ng * m), sn((size_t)ng * m), gv((size_t)ng * (m + 1)),
+        hcol((size_t)ng * hs), yv((size_t)ng * c->nscal, 0.0);
+    int its = 0, vcyc = 0;
+    bool fresh = false;   // rn holds the norms of the current residual
+    for (int g = 0; g < ng; ++g) active[g] = bn[g] > 0.0;
+    while (its < c->opt.max_iter) {
+        rc = group_norm2(c, c->V, rn.data());
+        if (rc) return rc;
+        fresh = true;
+        bool any = false;
+        for (int g = 0; g < ng; ++g) {
+            rn[g] = std::sqrt(rn[g]);
+            if (active[g] && rn[g] <= c->opt.rtol * bn[g]) active[g] = 0;
+            sig0[g] = active[g] ? 1.0 / rn[g] : 0.0;
+            any = any || active[g];
+        }
+        if (!any) break;
+        HIPCHK(c, hipMemcpyAsync(c->sig, sig0.data(), sizeof(double) * ng, hipMemcpyHostToDevice, c->stream));
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        for (int g = 0; g < ng; ++g) {
+            gv[(size_t)g * (m + 1)] = active[g] ? rn[g] : 0.0;
+            done[g] = !active[g];
+            jd[g] = 0;
+        }
+        int jmax = 0;
+        for (int j = 0; j < m && its < c->opt.max_iter; ++j) {
+            rc = precondition(c, c->V + (long long)j * c->ld, c->Z + (long long)j * c->ld, (double*)c->mbuf,
+                              c->sig + (long long)j * kSigStride);
+            if (rc) return rc;
+            vcyc += vc_per_it;
+            rc = apply_krylov(c, c->Z + (long long)j * c->ld, (const double*)c->mbuf, c->w, nullptr);
+            if (rc) return rc;
+            {
+                Timer t(c, C_REST);
+                rc = arnoldi_orth(c, j, hcol.data());
+                if (rc) return rc;
+            }
+            ++its;
+            jmax = j + 1;
+            bool all = true;
+            for (int g = 0; g < ng; ++g) {
+                if (done[g]) continue;
+                double* Hg = H.data() + (size_t)g * (m + 1) * m;
+                double *csg = cs.data() + (size_t)g * m, *sng = sn.data() + (size_t)g * m;
+                double* gg = gv.data() + (size_t)g * (m + 1);
+                const double* hc = hcol.data() + (size_t)g * hs;
+                for (int i = 0; i <= j + 1; ++i) Hg[(size_t)i * m + j] = hc[i];
+                for (int i = 0; i < j; ++i) {
+                    const double a = Hg[(size_t)i * m + j], b = Hg[(size_t)(i + 1) * m + j];
+                    Hg[(size_t)i * m + j] = csg[i] * a + sng[i] * b;
+                    Hg[(size_t)(i + 1) * m + j] = -sng[i] * a + csg[i] * b;
+                }
+                const double a = Hg[(size_t)j * m + j], b = Hg[(size_t)(j + 1) * m + j];
+                const double d = std::hypot(a, b);
+                csg[j] = d > 0 ? a / d : 1.0;
+                sng[j] = d > 0 ? b / d : 0.0;
+                Hg[(size_t)j * m + j] = d;
+                Hg[(size_t)(j + 1) * m + j] = 0.0;
+                gg[j + 1] = -sng[j] * gg[j];
+                gg[j] = csg[j] * gg[j];
+                jd[g] = j + 1;
+                if (c->cplx) ++st.block_iterations[g];
+                if (std::getenv("RK_DEBUG_ARNOLDI")) {
+                    std::fprintf(stderr, "[rk] g=%d j=%d |g|/bn=%.3e h:", g, j, std::fabs(gg[j + 1]) / bn[g]);
+                    for (int i = 0; i <= j + 1; ++i) std::fprintf(stderr, " %.6e", hc[i]);
+                    std::fprintf(stderr, "\n");
+                }
+                if (std::fabs(gg[j + 1]) <= c->opt.rtol * bn[g] || hc[j + 1] == 0.0) done[g] = 1;
+                else all = false;
+            }
+            if (all) break;
+        }
+        // y_g = H_g^-1 g_g (upper triangular) on the group's jd columns, k += Z y
+        std::fill(yv.begin(), yv.end(), 0.0);
+        for (int g = 0; g < ng; ++g) {
+            const double* Hg = H.data() + (size_t)g * (m + 1) * m;
+            const double* gg = gv.data() + (size_t)g * (m + 1);
+            double* yg = yv.data() + (size_t)g * c->nscal;
+            for (int i = jd[g] - 1; i >= 0; --i) {
+                double s = gg[i];
+                for (int l = i + 1; l < jd[g]; ++l) s -= Hg[(size_t)i * m + l] * yg[l];
+                yg[i] = s / Hg[(size_t)i * m + i];
+            }
+        }
+        {
+            Timer t(c, C_REST);
+            HIPCHK(c, hipMemcpyAsync(c->ycoef, yv.data(), sizeof(double) * yv.size(), hipMemcpyHostToDevice,
+                                     c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            HIPCHK(c, launch_combine(c->kv, RK_FP64, c->Z, jmax, c->ld, c->ycoef, c->nscal, c->seg, c->stream));
+        }
+        // true residual r = rhs - A k
+        HIPCHK(c, launch_stage_mix(RK_FP64, c->kv, RK_FP64, c->mbuf, c->mix + (c->cplx ? kMixCLam : kMixAinv),
+                                   c->Q, c->Q, c->N, c->stream));
+        rc = apply_krylov(c, c->kv, (const double*)c->mbuf, c->V, c->rhs);
+        if (rc) return rc;
+        fresh = false;
+    }
+    if (!fresh) {
+        rc = group_norm2(c, c->V, rn.data());
+        if (rc) return rc;
+        for (auto& v : rn) v = std::sqrt(v);
+    }
+    converged = true;
+    double worst = 0.0;
+    for (int g = 0; g < ng; ++g) {
+        const double rel = bn[g] > 0 ? rn[g] / bn[g] : 0.0;
+        worst = std::max(worst, rel);
+        if (bn[g] > 0 && rn[g] > c->opt.rtol * bn[g]) converged = false;
+    }
+    st.iterations = its;
+    st.vcycles = vcyc;
+    st.rel_residual = worst;
+    return RK_OK;
 }
 
 }  // namespace
@@ -596,6 +797,7 @@ void rk_default_options(rk_options* o) {
     o->eig_iterations = 30;
     o->eig_max = nullptr;
     o->timing = 0;
+    o->method = RK_METHOD_CROUT;
 }
 
 int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {
@@ -631,14 +833,38 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
     carve(*c, (char*)d_workspace);
     c->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return fail(nullptr, RK_EHIP, "no HIP device"); }
-    c->host_scal.assign(c->opt.restart + 16, 0.0);
+    c->host_scal.assign((size_t)c->nscal * ((Q + 1) / 2), 0.0);
     std::string msg;
     if (!build_tableau(Q, c->tab, msg)) { delete c; return fail(nullptr, RK_EINVAL, msg); }
     build_element(degree, c->el);
     for (int f = 0; f < F_NFORMS; ++f) c->form[f] = make_coeffs(*c, c->h, f);
     for (auto& L : c->lv) L.blk = make_coeffs(*c, L.h, F_BLOCKS);
-    // small Q x Q mixing data: S^-1, S, and the right-hand-side coefficients
-    std::vector<double> mix(8 * 81, 0.0);
+    {
+        const Tableau& t = c->tab;
+        const double h3 = c->h * c->h * c->h;
+        for (int j = 0; j < t.npair; ++j) c->presb_m.alpha[t.nb + j] = t.clam_im[j] * h3;
+        // Krylov systems: one over all stages, or one per block of slots
+        c->ng = c->cplx ? t.nb : 1;
+        Segs sg;
+        sg.ngroup = c->ng;
+        int q = 0;
+        for (int g = 0; g < c->ng; ++g) {
+            sg.first[g] = q;
+            if (!c->cplx) { sg.off[q] = 0; sg.len[q] = (long long)Q * c->N3; ++q; continue; }
+            const int slots[2] = {g, t.nb + g};
+            for (int i = 0; i < (g < t.npair ? 2 : 1); ++i) {
+                sg.off[q] = (long long)slots[i] * c->N3;
+                sg.len[q] = c->N3;
+                c->slot_group.v[slots[i]] = g;
+                ++q;
+            }
+        }
+        sg.first[c->ng] = q;
+        c->seg = sg;
+    }
+    // small Q x Q mixing data: S^-1, S, the right-hand-side coefficients, and
+    // the slot mixes of the complex method
+    std::vector<double> mix(kMixSlots * 81, 0.0);
     for (int i = 0; i < Q; ++i)
         for (int j = 0; j < Q; ++j) {
             double as = 0.0;
@@ -650,6 +876,26 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
         mix[kMixS + i] = c->tab.S[i];
         mix[kMixAinv + i] = c->tab.Ainv[i];
         mix[kMixA + i] = c->tab.A[i];
+        mix[kMixCLam + i] = c->tab.CLam[i];
+    }
+    {
+        // PRESB (eq. presb:p) around the two block solves: per pair j the
+        // inputs are (r_re + r_im, r_im) on slots (j, nb + j) and the outputs
+        // (g1 - g2, g2); the real block passes through.  LamPout = Lam_r Pout.
+        const Tableau& t = c->tab;
+        double* pin = mix.data() + kMixPin;
+        double* pout = mix.data() + kMixPout;
+        for (int s = 0; s < Q; ++s) { pin[s * Q + s] = 1.0; pout[s * Q + s] = 1.0; }
+        for (int j = 0; j < t.npair; ++j) {
+            pin[j * Q + t.nb + j] = 1.0;
+            pout[j * Q + t.nb + j] = -1.0;
+        }
+        for (int i = 0; i < Q; ++i)
+            for (int j = 0; j < Q; ++j) {
+                double acc = 0.0;
+                for (int l = 0; l < Q; ++l) acc += t.CLam[i * Q + l] * pout[l * Q + j];
+                mix[kMixLamPout + i * Q + j] = acc;
+            }
     }
     hipError_t e = hipMemcpyAsync(c->mix, mix.data(), mix.size() * 8, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -687,6 +933,10 @@ int rk_info(const rk_ctx* c, rk_info_t* o) {
     }
     for (int i = 0; i < Q; ++i) { o->b[i] = c->tab.b[i]; o->c[i] = c->tab.c[i]; o->lambda[i] = c->tab.lam[i]; }
     for (int i = 0; i <= c->k; ++i) o->nodes[i] = c->el.nodes[i];
+    o->n_blocks = c->tab.nb;
+    o->n_pairs = c->tab.npair;
+    for (int i = 0; i < Q; ++i) { o->clam_re[i] = c->tab.clam_re[i]; o->clam_im[i] = c->tab.clam_im[i]; }
+    for (int i = 0; i < Q * Q; ++i) { o->T[i] = c->tab.CT[i]; o->U[i] = c->tab.CU[i]; }
     return RK_OK;
 }
 
@@ -702,10 +952,10 @@ int rk_apply_operator(rk_ctx* c, int form, int dtype, const void* u, void* v) {
     const Coeffs& cf = c->form[form];
     if (!cf.pair) return op(c, c->k, dtype, EPI_STORE, cf, u, v, nullptr, nullptr, c->n, 0, ns, 0, 0);
     // dense forms: mix the input once, then the pair operator
-    const double* D = c->mix + (cf.premix == 1 ? kMixAinv : kMixA);
+    const double* D = c->mix + (cf.premix == 1 ? kMixAinv : cf.premix == 2 ? kMixA : kMixCLam);
     HIPCHK(c, launch_stage_mix(dtype, u, dtype, c->mbuf, D, c->Q, c->Q, c->N, c->stream));
-    const void* um = cf.premix == 1 ? c->mbuf : u;
-    const void* uk = cf.premix == 1 ? u : c->mbuf;
+    const void* um = cf.premix != 2 ? c->mbuf : u;
+    const void* uk = cf.premix != 2 ? u : c->mbuf;
     return op(c, c->k, dtype, EPI_STORE, cf, um, v, nullptr, nullptr, c->n, 0, ns, 0, 0, uk);
 }
 
@@ -730,109 +980,47 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
     if (!c) return RK_EINVAL;
     if (!y) return fail(c, RK_EINVAL, "y is NULL");
     if (G && !gamma) return fail(c, RK_EINVAL, "gamma is NULL while G is given");
-    const int Q = c->Q, m = c->opt.restart;
-    const long long qn = (long long)Q * c->N3;
+    const int Q = c->Q;
     c->pool_used = 0;
     rk_stats st{};
     int rc;
-    // Right-hand side of eq. (irk:A): rhs_i = sum_j Ainv_ij (gamma_j G - K y).
+    // Right-hand side of eq. (irk:A): rhs_i = sum_j Ainv_ij (gamma_j G - K y);
+    // for the complex method directly in slots, (T (x) I) rhs.
     {
         Timer t(c, C_RHS);
         rc = op(c, c->k, RK_FP64, EPI_STORE, c->form[F_K], y, c->Ky, nullptr, nullptr, c->n, 0, 1, 0, 0);
         if (rc) return rc;
-        double cf[2 * RK_MAX_Q];
+        double c1[RK_MAX_Q], c2[RK_MAX_Q], cf[2 * RK_MAX_Q];
         for (int i = 0; i < Q; ++i) {
-            double c1 = 0.0, c2 = 0.0;
+            c1[i] = 0.0; c2[i] = 0.0;
             for (int j = 0; j < Q; ++j) {
-                c1 += c->tab.Ainv[i * Q + j] * (G ? gamma[j] : 0.0);
-                c2 -= c->tab.Ainv[i * Q + j];
+                c1[i] += c->tab.Ainv[i * Q + j] * (G ? gamma[j] : 0.0);
+                c2[i] -= c->tab.Ainv[i * Q + j];
             }
-            cf[i] = c1; cf[RK_MAX_Q + i] = c2;
+        }
+        for (int i = 0; i < Q; ++i) {
+            if (!c->cplx) { cf[i] = c1[i]; cf[RK_MAX_Q + i] = c2[i]; continue; }
+            double a = 0.0, b = 0.0;
+            for (int j = 0; j < Q; ++j) { a += c->tab.CT[i * Q + j] * c1[j]; b += c->tab.CT[i * Q + j] * c2[j]; }
+            cf[i] = a; cf[RK_MAX_Q + i] = b;
         }
         HIPCHK(c, hipMemcpyAsync(c->mix + kMixRhs, cf, sizeof(cf), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));   // cf lives on the host stack
         HIPCHK(c, launch_rhs_mix(G, c->Ky, c->rhs, c->mix + kMixRhs, c->mix + kMixRhs + RK_MAX_Q, Q, c->N, c->stream));
     }
-    const double bnorm = std::sqrt(device_norm2(c, c->rhs, qn, &rc));
+    bool converged = false;
+    rc = gmres(c, st, converged);
     if (rc) return rc;
-    HIPCHK(c, launch_fill(RK_FP64, c->kv, qn, 0.0, c->stream));
-    // the residual of each restart cycle lives in Vhat_0 (k_0 = 0: r = rhs)
-    HIPCHK(c, launch_copy(RK_FP64, c->rhs, c->V, qn, c->stream));
-    int its = 0, vcyc = 0;
-    double rnorm = bnorm;
-    bool converged = bnorm == 0.0;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), yv(m);
-    while (!converged && its < c->opt.max_iter) {
-        rnorm = std::sqrt(device_norm2(c, c->V, qn, &rc, c->sig));   // sig[0] = 1/||r||
-        if (rc) return rc;
-        if (rnorm <= c->opt.rtol * bnorm) { converged = true; break; }
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = rnorm;
-        int jd = 0;
-        for (int j = 0; j < m && its < c->opt.max_iter; ++j) {
-            rc = precondition(c, c->V + (long long)j * c->ld, c->Z + (long long)j * c->ld, (double*)c->mbuf,
-                              c->sig + j);
-            if (rc) return rc;
-            vcyc += c->opt.mode == RK_BATCHED ? 1 : Q;
-            rc = apply_cala(c, c->Z + (long long)j * c->ld, (const double*)c->mbuf, c->w, nullptr);
-            if (rc) return rc;
-            {
-                Timer t(c, C_REST);
-                rc = arnoldi_orth(c, j, hcol.data());
-                if (rc) return rc;
-            }
-            for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = hcol[i];
-            for (int i = 0; i < j; ++i) {
-                const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-            }
-            const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
-            const double d = std::hypot(a, b);
-            cs[j] = d > 0 ? a / d : 1.0;
-            sn[j] = d > 0 ? b / d : 0.0;
-            H[(size_t)j * m + j] = d;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++its;
-            jd = j + 1;
-            if (std::getenv("RK_DEBUG_ARNOLDI")) {
-                std::fprintf(stderr, "[rk] j=%d |g|/bn=%.3e h:", j, std::fabs(g[j + 1]) / bnorm);
-                for (int i = 0; i <= j + 1; ++i) std::fprintf(stderr, " %.6e", hcol[i]);
-                std::fprintf(stderr, "\n");
-            }
-            if (std::fabs(g[j + 1]) <= c->opt.rtol * bnorm || hcol[j + 1] == 0.0) break;
-        }
-        // y = H^-1 g (upper triangular), k += Z y
-        for (int i = jd - 1; i >= 0; --i) {
-            double s = g[i];
-            for (int l = i + 1; l < jd; ++l) s -= H[(size_t)i * m + l] * yv[l];
-            yv[i] = s / H[(size_t)i * m + i];
-        }
-        {
-            Timer t(c, C_REST);
-            HIPCHK(c, hipMemcpyAsync(c->ycoef, yv.data(), sizeof(double) * jd, hipMemcpyHostToDevice, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            HIPCHK(c, launch_combine(c->kv, RK_FP64, c->Z, jd, c->ld, c->ycoef, qn, c->stream));
-        }
-        // true residual r = rhs - A k
-        HIPCHK(c, launch_stage_mix(RK_FP64, c->kv, RK_FP64, c->mbuf, c->mix + kMixAinv, Q, Q, c->N, c->stream));
-        rc = apply_cala(c, c->kv, (const double*)c->mbuf, c->V, c->rhs);
-        if (rc) return rc;
-    }
-    if (!converged) {
-        rnorm = std::sqrt(device_norm2(c, c->V, qn, &rc));
-        if (rc) return rc;
-        converged = rnorm <= c->opt.rtol * bnorm;
-    }
-    st.iterations = its;
-    st.vcycles = vcyc;
-    st.rel_residual = bnorm > 0 ? rnorm / bnorm : 0.0;
     if (converged) {
         Timer t(c, C_REST);
-        HIPCHK(c, launch_stage_combine(y, c->kv, c->tab.b, c->tau, Q, c->N, c->stream));
+        // y += tau sum_i b_i k_i with k = (U (x) I) u for the complex method
+        double bw[RK_MAX_Q];
+        for (int s = 0; s < Q; ++s) {
+            if (!c->cplx) { bw[s] = c->tab.b[s]; continue; }
+            bw[s] = 0.0;
+            for (int i = 0; i < Q; ++i) bw[s] += c->tab.b[i] * c->tab.CU[i * Q + s];
+        }
+        HIPCHK(c, launch_stage_combine(y, c->kv, bw, c->tau, Q, c->N, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (c->opt.timing) {
@@ -846,7 +1034,7 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
         st.t_blocks = tt[C_BLOCKS]; st.t_rest = tt[C_REST];
     }
     if (stats) *stats = st;
-    if (!converged) return fail(c, RK_ENOCONV, "FGMRES did not reach rtol within max_iter");
+    if (!converged) return fail(c, RK_ENOCONV, "GMRES did not reach rtol within max_iter");
     return RK_OK;
 }
 

@@ -24,6 +24,17 @@ struct Tableau {
     double L[RK_MAX_Q * RK_MAX_Q], U[RK_MAX_Q * RK_MAX_Q];
     double S[RK_MAX_Q * RK_MAX_Q], Sinv[RK_MAX_Q * RK_MAX_Q];
     double lam[RK_MAX_Q];
+    // Direct diagonalisation A^-1 = S Lam S^-1 with complex S, Lam (eq.
+    // irk:Ainv) in real slot form: nb = ceil(Q/2) blocks, the npair
+    // conjugate pairs (one member each, Im > 0, ascending Re) then the real
+    // eigenvalue (odd Q).  Slots 0..nb-1 hold the real parts (and the real
+    // block), slots nb..Q-1 the imaginary parts, so pair j owns slots j and
+    // nb + j.  slots = (CT (x) I) k, k = (CU (x) I) slots, and
+    // CT A^-1 CU = CLam with [[a, -b], [b, a]] per pair lam = a + i b.
+    int nb = 0, npair = 0;
+    double clam_re[RK_MAX_Q], clam_im[RK_MAX_Q];
+    double CT[RK_MAX_Q * RK_MAX_Q], CU[RK_MAX_Q * RK_MAX_Q], CLam[RK_MAX_Q * RK_MAX_Q];
+    double hshift[RK_MAX_Q];   // per slot: a + b for a pair's slots, lam for the real block
 };
 // Returns false (with a message) if a factorisation breaks down.
 bool build_tableau(int Q, Tableau& t, std::string& err);
@@ -46,6 +57,24 @@ void build_element(int k, Element1D& e);
 struct StageScal {
     double alpha[RK_MAX_Q] = {};
     double beta[RK_MAX_Q] = {};
+};
+
+// Independent systems inside one Krylov vector.  Group g (the unknowns of
+// one block) is the union of the vector segments q = first[g] .. first[g+1]-1,
+// segment q covering elements [off[q], off[q] + len[q]).  The Crout solve
+// has one group of one segment (the whole vector); the complex solve has one
+// group per block and one segment per slot.
+struct Segs {
+    int ngroup = 1;
+    int first[RK_MAX_Q + 1] = {0, 1};
+    long long off[RK_MAX_Q] = {};
+    long long len[RK_MAX_Q] = {};
+};
+// Per-group scalars of Krylov vector i live at [i * kSigStride + g].
+constexpr int kSigStride = RK_MAX_Q;
+// A slot -> index map (passed by value).
+struct SlotIdx {
+    int v[RK_MAX_Q] = {};
 };
 
 // ---------------------------------------------------------------------------
@@ -101,34 +130,40 @@ hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* 
 // out_i = sum_j D[i][j] in_j (D: device doubles, row-major Qout x Qin),
 // computed in double; in/out dtypes independent.  Boundary entries 0.  If out2
 // is not null, out2_i = sum_j D2[i][j] in_j (fp64) is written in the same pass.
-// If in_scale (device scalar) is not null the input is multiplied by it first.
+// If in_scale (device doubles) is not null, input slot j is multiplied by
+// in_scale[scale_idx->v[j]] first (scale_idx null: in_scale[0] for all).
 hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* out,
                             const double* D, int qout, int qin, int N, hipStream_t st,
                             double* out2 = nullptr, const double* D2 = nullptr,
-                            const double* in_scale = nullptr);
+                            const double* in_scale = nullptr, const SlotIdx* scale_idx = nullptr);
 
 // out_i = c1[i] G + c2[i] w on interior nodes, 0 on boundary nodes (fp64, N
 // nodes per direction); G may be null.  c1, c2: device doubles.
 hipError_t launch_rhs_mix(const double* G, const double* w, double* out, const double* c1,
                           const double* c2, int Q, int N, hipStream_t st);
 
-// Partial dot products: part[blk * nout + l] = sum_{i in blk} X_l[i] * w[i] for
-// l < nvec, and (if self) part[blk * nout + nvec] = sum w[i]^2, nout = nvec + self.
-hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w, long long n,
+// Partial dot products per group g of sg (workgroup blk of nblocks):
+// part[(g nblocks + blk) nout + l] = sum over the group's entries in blk of
+// X_l[i] w[i] for l < nvec, and (if self) at l = nvec of w[i]^2;
+// nout = nvec + self.
+hipError_t launch_dots(const double* X, int nvec, long long ld, const double* w, const Segs& sg,
                        int self, double* part, int nblocks, hipStream_t st);
-// out = w - sum_l h[l] sig[l] X_l (sig may be null = ones; out may alias w);
-// if norm_part: norm_part[blk] = sum out^2 over the block's entries.
-hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, const double* sig,
-                            const double* w, double* out, long long n, double* norm_part, int nblocks,
-                            hipStream_t st);
-// out[l] (+)= scale[l] * sum_b part[b * nout + l] for l < nout (fixed order;
-// scale applies to l < nscale).  If inv_sqrt_out: *inv_sqrt_out = 1/sqrt(out[nout-1]).
+// Per group g: out = w - sum_l h[g hstride + l] sig[l kSigStride + g] X_l
+// (sig may be null = ones; out may alias w); if norm_part:
+// norm_part[g nblocks + blk] = sum of out^2 over the group's entries in blk.
+hipError_t launch_gs_update(const double* X, int nvec, long long ld, const double* h, int hstride,
+                            const double* sig, const double* w, double* out, const Segs& sg,
+                            double* norm_part, int nblocks, hipStream_t st);
+// For g < ngroup and l < nout: out[g ostride + l] (+)= scale[l kSigStride + g]
+// * sum_b part[(g nblocks + b) nout + l] (fixed order; scale applies to
+// l < nscale).  If inv_sqrt_out: inv_sqrt_out[g] = 1/sqrt(out[g ostride + nout-1]).
 hipError_t launch_reduce(const double* part, int nblocks, int nout, double* out, int accumulate,
                          hipStream_t st, const double* scale = nullptr, int nscale = 0,
-                         double* inv_sqrt_out = nullptr);
-// k += sum_j y[j] Z_j   (Z fp64 or fp32)
+                         double* inv_sqrt_out = nullptr, int ngroup = 1, int ostride = 0);
+// Per group g: k += sum_j y[g ystride + j] Z_j over the group's entries
+// (Z fp64 or fp32)
 hipError_t launch_combine(double* kv, int dtype_z, const void* Z, int nz, long long ld,
-                          const double* y, long long n, hipStream_t st);
+                          const double* y, int ystride, const Segs& sg, hipStream_t st);
 // y += tau sum_i b[i] k_i on interior nodes, y = 0 on boundary nodes
 // (b: host values, passed by value; N nodes per direction)
 hipError_t launch_stage_combine(double* y, const double* kv, const double* b, double tau, int Q,

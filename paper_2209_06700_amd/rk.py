@@ -13,15 +13,16 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import (LIB, RK_BATCHED, RK_ENOCONV, RK_FP32, RK_FP64, RK_OK, RK_OP_BLOCKS, RK_OP_CALA,
-                   RK_MAX_Q, RK_OP_K, RK_OP_M, RK_OP_STAGE, RK_PER_STAGE, RK_PREC_FP64, RK_PREC_MIXED,
-                   rk_info_t, rk_mesh, rk_options, rk_stats)
+from ._lib import (LIB, RK_BATCHED, RK_ENOCONV, RK_FP32, RK_FP64, RK_METHOD_COMPLEX, RK_METHOD_CROUT, RK_OK,
+                   RK_OP_BLOCKS, RK_OP_CALA, RK_OP_CBLOCKS, RK_MAX_Q, RK_OP_K, RK_OP_M, RK_OP_STAGE,
+                   RK_PER_STAGE, RK_PREC_FP64, RK_PREC_MIXED, rk_info_t, rk_mesh, rk_options, rk_stats)
 
 __all__ = ["RKError", "rk_default_options", "rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info",
            "rk_step", "rk_step_batch", "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner",
            "rk_last_error",
            "RadauIIA", "RK_FP64", "RK_FP32", "RK_PREC_FP64", "RK_PREC_MIXED", "RK_BATCHED",
-           "RK_PER_STAGE", "RK_OP_CALA", "RK_OP_STAGE", "RK_OP_BLOCKS", "RK_OP_K", "RK_OP_M"]
+           "RK_PER_STAGE", "RK_OP_CALA", "RK_OP_STAGE", "RK_OP_BLOCKS", "RK_OP_K", "RK_OP_M",
+           "RK_OP_CBLOCKS", "RK_METHOD_CROUT", "RK_METHOD_COMPLEX"]
 
 
 class RKError(RuntimeError):
@@ -54,7 +55,8 @@ def _check(rc: int, ctx: Context | None = None):
 def rk_default_options(**kw) -> rk_options:
     """Options struct with the library defaults, overridden by keywords
     (precision, mode, rtol, max_iter, restart, cheb_degree, coarse_cheb_degree,
-    cheb_range, eig_safety, eig_iterations, timing; eig_max is set by rk_create)."""
+    cheb_range, eig_safety, eig_iterations, timing, method; eig_max is set by
+    rk_create)."""
     o = rk_options()
     LIB.rk_default_options(C.byref(o))
     for k, v in kw.items():
@@ -142,7 +144,10 @@ def rk_info(ctx: Context) -> dict:
                 level_cells=list(i.level_cells[:nl]), tau=i.tau, h=i.h,
                 A=mat(i.A), b=list(i.b[:Q]), c=list(i.c[:Q]), Ainv=mat(i.Ainv), L=mat(i.L),
                 S=mat(i.S), Sinv=mat(i.Sinv), lam=list(i.lambda_[:Q]),
-                eig_max=list(i.eig_max[:nl]), nodes=list(i.nodes[:i.degree + 1]))
+                eig_max=list(i.eig_max[:nl]), nodes=list(i.nodes[:i.degree + 1]),
+                n_blocks=i.n_blocks, n_pairs=i.n_pairs,
+                clam=[complex(i.clam_re[j], i.clam_im[j]) for j in range(i.n_blocks)],
+                T=mat(i.T), U=mat(i.U))
 
 
 def rk_step(ctx: Context, t_n: float, y: torch.Tensor, G: torch.Tensor | None = None,
@@ -168,7 +173,7 @@ def rk_step(ctx: Context, t_n: float, y: torch.Tensor, G: torch.Tensor | None = 
 def _stats_dict(rc, st):
     return dict(code=rc, iterations=st.iterations, vcycles=st.vcycles, rel_residual=st.rel_residual,
                 t_rhs=st.t_rhs, t_vmult=st.t_vmult, t_basis=st.t_basis, t_blocks=st.t_blocks,
-                t_rest=st.t_rest)
+                t_rest=st.t_rest, block_iterations=list(st.block_iterations))
 
 
 def rk_step_batch(ctxs, t_n, ys, Gs=None, gammas=None, threads: int = 0, raise_on_error: bool = True):

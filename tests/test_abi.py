@@ -4,6 +4,8 @@ validation) behave as documented.  No GPU is touched here."""
 import ctypes as C
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -39,6 +41,39 @@ def test_default_options():
     assert o.precision == 1 and o.restart == 12
     with pytest.raises(TypeError):
         R.rk_default_options(bogus=1)
+
+
+def test_default_method_and_bad_method():
+    from paper_2209_06700_amd import rk as R
+    assert R.rk_default_options().method == R.RK_METHOD_CROUT
+    with pytest.raises(R.RKError):
+        R.rk_workspace_bytes(4, 2, 2, R.rk_default_options(method=7))
+    assert R.rk_workspace_bytes(4, 2, 3, R.rk_default_options(method=R.RK_METHOD_COMPLEX)) > 0
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_struct_layout_matches_header(tmp_path):
+    """sizeof and every field offset of the ABI structs, as a C compiler lays
+    them out from include/rk.h, equal the ctypes mirrors in the binding."""
+    from paper_2209_06700_amd import _lib
+    structs = {"rk_options": _lib.rk_options, "rk_stats": _lib.rk_stats, "rk_info_t": _lib.rk_info_t}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rk.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            cf = "lambda" if f == "lambda_" else f
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {cf}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        name, field, val = line.split()
+        cls = structs[name]
+        want = C.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(val) == want, line
 
 
 def test_workspace_bytes_scale_with_problem():
