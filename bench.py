@@ -150,11 +150,16 @@ def time_op(torch, R, ctx, form, u, v, reps):
 
 
 RTOLS = (1e-6, 1e-7, 1e-8, 1e-9, 1e-10)
+# the complex method's stopping test is per block in the eigenbasis of A^-1:
+# it needs tighter tolerances for the same accuracy of y
+RTOLS_COMPLEX = (1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12)
 
 
-def time_steps(torch, R, n, k, Q, tau, steps, warmup, y0, **opts):
+def time_steps(torch, R, n, k, Q, tau, steps, warmup, y0, blocks=None, **opts):
     """Average wall time of `steps` Radau IIA steps after `warmup` steps, from
-    the seeded initial data, synchronised on both sides; FGMRES iterations."""
+    the seeded initial data, synchronised on both sides; FGMRES iterations.
+    With a list `blocks`, the per-block iteration counts of every step are
+    appended to it (complex method)."""
     s = R.RadauIIA(n, k, Q, tau, **opts)
     y = y0.clone()
     t = 0.0
@@ -168,6 +173,8 @@ def time_steps(torch, R, n, k, Q, tau, steps, warmup, y0, **opts):
         st = s.step(t, y)
         its.append(st["iterations"])
         vcs.append(st["vcycles"])
+        if blocks is not None:
+            blocks.append(st["block_iterations"][:(Q + 1) // 2])
         t += tau
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(steps, 1)
@@ -214,11 +221,13 @@ def cpu_baseline_leg(torch, R, n=16, k=4, Q=4, tau=5e-4, budget_s=12.0):
     ref = ModalSolver(na, k).step(RadauIIA(Qa), tau, inner(y0))
     t_oracle = time.perf_counter() - t0
     acc = {"grid": "32^3 cells Q_4, Q=4, tau=5e-4, same seeded data", "oracle_modal_step_s": t_oracle,
-           "mixed_batched": {}, "fp64_per_stage": {}}
-    for name, prec, mode in (("mixed_batched", R.RK_PREC_MIXED, R.RK_BATCHED),
-                             ("fp64_per_stage", R.RK_PREC_FP64, R.RK_PER_STAGE)):
-        for rtol in RTOLS:
-            s = R.RadauIIA(na, k, Qa, tau, precision=prec, mode=mode, rtol=rtol)
+           "mixed_batched": {}, "fp64_per_stage": {}, "complex_presb_mixed_batched": {}}
+    for name, prec, mode, method, rtols in (
+            ("mixed_batched", R.RK_PREC_MIXED, R.RK_BATCHED, R.RK_METHOD_CROUT, RTOLS),
+            ("fp64_per_stage", R.RK_PREC_FP64, R.RK_PER_STAGE, R.RK_METHOD_CROUT, RTOLS),
+            ("complex_presb_mixed_batched", R.RK_PREC_MIXED, R.RK_BATCHED, R.RK_METHOD_COMPLEX, RTOLS_COMPLEX)):
+        for rtol in rtols:
+            s = R.RadauIIA(na, k, Qa, tau, precision=prec, mode=mode, rtol=rtol, method=method)
             y = torch.tensor(y0, device="cuda")
             st = s.step(0.0, y)
             err = float(np.linalg.norm(inner(y.cpu().numpy()) - ref) / np.linalg.norm(ref))
@@ -283,7 +292,7 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20):
 def loosest_rtol(acc_runs, bound=1e-8):
     """The loosest FGMRES tolerance whose step error is within `bound`."""
     ok = [float(r) for r, v in acc_runs.items() if v["rel_l2_error"] <= bound]
-    return max(ok) if ok else min(RTOLS)
+    return max(ok) if ok else min(float(r) for r in acc_runs)
 
 
 def main():
@@ -295,6 +304,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host leg (oracle)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 per-stage comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven batch of 64 problems")
+    ap.add_argument("--no-complex", action="store_true",
+                    help="skip the direct complex diagonalisation (PRESB) comparison")
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--cheb-degree", type=int, default=None, help="smoother degree (library default if unset)")
     ap.add_argument("--cheb-range", type=float, default=None, help="Chebyshev range (library default if unset)")
@@ -377,6 +388,17 @@ def main():
     if not args.no_plain:
         t_plain, its_plain, _ = time_steps(torch, R, n, k, Q, tau, ps, 1, y0, rtol=1e-10, **plain)
         log(f"[bench] plain fp64 per-stage: {t_plain * 1e3:.2f} ms/step, its {its_plain}")
+    # the direct complex diagonalisation with PRESB on the same workload
+    cx = None
+    if not args.no_complex:
+        blk = []
+        t_cx, its_cx, vcs_cx = time_steps(torch, R, n, k, Q, tau, args.steps, 1, y0, blocks=blk, rtol=1e-10,
+                                          method=R.RK_METHOD_COMPLEX, **mixed)
+        cx = {"method": "direct complex diagonalisation, per-block GMRES with PRESB (two V-cycles on "
+                        "(Re lam + Im lam) M + tau K per pair)",
+              "rtol": 1e-10, "ms_per_step": t_cx * 1e3, "lockstep_iterations": its_cx,
+              "block_iterations": blk, "vcycle_sequences": vcs_cx}
+        log(f"[bench] complex PRESB: {t_cx * 1e3:.2f} ms/step, block its {blk[-1]}")
     at_acc = None
     cpu = acc = None
     if not args.no_cpu:
@@ -392,6 +414,14 @@ def main():
             at_acc["fp64_per_stage"] = {"rtol": r_plain, "ms_per_step": tp * 1e3, "fgmres_iterations": ip}
             at_acc["speedup"] = tp / tm
             log(f"[bench] at 1e-8 accuracy: plain fp64 per-stage {tp * 1e3:.2f} ms (rtol {r_plain:.0e})")
+        if not args.no_complex:
+            r_cx = loosest_rtol(acc["complex_presb_mixed_batched"])
+            blk = []
+            tc, ic, _ = time_steps(torch, R, n, k, Q, tau, args.steps, 1, y0, blocks=blk, rtol=r_cx,
+                                   method=R.RK_METHOD_COMPLEX, **mixed)
+            at_acc["complex_presb_mixed_batched"] = {"rtol": r_cx, "ms_per_step": tc * 1e3,
+                                                     "lockstep_iterations": ic, "block_iterations": blk[-1]}
+            log(f"[bench] at 1e-8 accuracy: complex PRESB {tc * 1e3:.2f} ms (rtol {r_cx:.0e})")
     del y0
     torch.cuda.empty_cache()
     batch = None
@@ -426,6 +456,7 @@ def main():
         "plain_fp64_per_stage": None if t_plain is None else {
             "ms_per_step": t_plain * 1e3, "fgmres_iterations": its_plain, "rtol": 1e-10,
             "speedup_of_mixed_batched": t_plain / t_step},
+        "complex_presb": cx,
         "at_1e-8_accuracy": at_acc,
         "uneven_batch": batch,
         "step_breakdown_s": {k2: breakdown[k2] for k2 in ("t_rhs", "t_vmult", "t_basis", "t_blocks", "t_rest")},
