@@ -28,4 +28,7 @@ complex_irk  direct diagonalisation A_Q^-1 = S Lam S^-1 (eq. irk:Ainv) in
            step that solves every block with its own GMRES.
 pointwise  single rows of the assembled operators, for sampled checks on
            meshes too large to assemble.
+deformed   mass and stiffness matrices on a smoothly deformed (non-affine)
+           hexahedral mesh with per-quadrature-point Jacobians, and sampled
+           rows for meshes too large to assemble.
 """

@@ -1,0 +1,97 @@
+"""Pins of the oracle's deformed-mesh matrices: the affine case, the analytic
+Jacobian, and integrals over the physical domain whose exact values are known
+(volume, the energy of the coordinate functions, the mean of x_1)."""
+import numpy as np
+import pytest
+
+from oracle.assemble import Mesh, Problem
+from oracle.deformed import DeformedProblem, assemble, phi, phi_jacobian, sampled_rows
+
+
+@pytest.mark.parametrize("n,k", [(2, 2), (3, 1), (2, 3)])
+def test_zero_deformation_is_the_affine_mesh(n, k):
+    p = Problem(n, k, "cell")
+    M, K = assemble(Mesh(n, k), 0.0)
+    assert abs(M - p.Mfull).max() <= 1e-15 * abs(p.Mfull).max()
+    assert abs(K - p.Kfull).max() <= 1e-14 * abs(p.Kfull).max()
+
+
+def test_jacobian_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0, 1, (50, 3))
+    eps, d = 0.15, 1e-6
+    J = phi_jacobian(x, eps)
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = d
+        fd = (phi(x + e, eps) - phi(x - e, eps)) / (2 * d)
+        np.testing.assert_allclose(J[:, :, j], fd, atol=1e-8)
+
+
+def test_boundary_is_fixed():
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0, 1, (40, 3))
+    for d in range(3):
+        for v in (0.0, 1.0):
+            y = x.copy()
+            y[:, d] = v
+            np.testing.assert_allclose(phi(y, 0.2), y, atol=1e-15)
+
+
+def _coordinate_interpolants(mesh, eps):
+    """Nodal values of the physical coordinates x_1, x_2, x_3 at the mapped nodes."""
+    X = np.stack(np.meshgrid(mesh.x1d, mesh.x1d, mesh.x1d, indexing="ij"), axis=-1)   # [x, y, z]
+    X = X.transpose(2, 1, 0, 3).reshape(-1, 3)                                       # x fastest
+    return phi(X, eps).T
+
+
+@pytest.mark.parametrize("n,k", [(4, 3), (3, 4)])
+def test_physical_integrals(n, k):
+    """With u_d the interpolant of the physical coordinate x_d (not in the
+    space on a curved mesh, but close to it): u_d^T K u_e -> delta_de |Omega| = delta_de,
+    1^T M u_1 -> int x_1 = 1/2, 1^T M 1 = |Omega| = 1, K 1 = 0."""
+    eps = 0.1
+    mesh = Mesh(n, k)
+    M, K = assemble(mesh, eps)
+    U = _coordinate_interpolants(mesh, eps)
+    one = np.ones(mesh.ndofs)
+    assert abs(K @ one).max() <= 1e-12 * abs(K).max()
+    assert abs(one @ M @ one - 1.0) <= 1e-10
+    G = U @ (K @ U.T)
+    np.testing.assert_allclose(G, np.eye(3), atol=2e-5)
+    assert abs(one @ M @ U[0] - 0.5) <= 1e-6
+
+
+def test_physical_integrals_converge():
+    """The coordinate-energy error shrinks under refinement (interpolation error
+    of the curved map), so the agreement above is not a coincidence."""
+    eps, k = 0.15, 2
+    errs = []
+    for n in (2, 4, 8):
+        mesh = Mesh(n, k)
+        _, K = assemble(mesh, eps)
+        U = _coordinate_interpolants(mesh, eps)
+        errs.append(np.abs(U @ (K @ U.T) - np.eye(3)).max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < errs[0] / 10
+
+
+def test_matrices_symmetric_and_definite():
+    p = DeformedProblem(3, 2, 0.12)
+    assert abs(p.M - p.M.T).max() <= 1e-15 and abs(p.K - p.K.T).max() <= 1e-13
+    assert np.linalg.eigvalsh(p.M.toarray()).min() > 0
+    assert np.linalg.eigvalsh(p.K.toarray()).min() > 0
+
+
+def test_sampled_rows_equal_assembled_rows():
+    n, k, eps = 3, 3, 0.1
+    mesh = Mesh(n, k)
+    M, K = assemble(mesh, eps)
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal(mesh.ndofs)
+    u[~mesh.interior_mask()] = 0
+    N = mesh.N
+    nodes = [(1, 1, 1), (3, 3, 3), (3, 5, 6), (8, 2, 7), (4, 4, 1)]
+    m, kk = sampled_rows(n, k, eps, u, nodes)
+    rows = [a + N * (b + N * c) for a, b, c in nodes]
+    np.testing.assert_allclose(m, (M @ u)[rows], atol=1e-15)
+    np.testing.assert_allclose(kk, (K @ u)[rows], atol=1e-12)
