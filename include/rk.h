@@ -235,8 +235,40 @@ int rk_vcycle(rk_ctx* ctx, int dtype, const void* d_b, void* d_x);
    r and z must not overlap.  Asynchronous. */
 int rk_apply_preconditioner(rk_ctx* ctx, const double* d_r, double* d_z);
 
-/* Message of the last failed call on ctx (or of the last failed rk_create
-   when ctx is NULL).  The pointer stays valid until the next call. */
+/* ---------------------------------------------------------------------------
+ * Deformed (non-affine) meshes: the operator only (no solver).  The paper
+ * works on affine meshes; Sec. 3.4 gives per-quadrature-point geometry as the
+ * data that batching the stages amortises.  The mesh here is the uniform
+ * n_cells^3 mesh of the unit cube mapped by
+ *     Phi(x) = x + eps sin(pi x1) sin(pi x2) sin(pi x3) (1, 1, 1),
+ * the identity on the boundary, with the same Q_k reference element and
+ * (k+1)^3-point Gauss rule as the affine mesh; Dirichlet conditions and the
+ * vector layout as above (node (ix,iy,iz) is the image of the affine node).
+ * Errors of these context-free calls are reported by rk_last_error(NULL).
+ * ------------------------------------------------------------------------- */
+#define RK_MAX_DEFORM 0.1   /* |eps| <= 0.1 keeps det Phi' >= 0.05 */
+
+/* Bytes of the geometry array (dtype RK_FP64 or RK_FP32): per cell and
+   Gauss point 7 values, w det J and the symmetric w det J J^-1 J^-T. */
+int rk_deformed_geometry_bytes(const rk_mesh* mesh, int degree, int dtype, size_t* bytes);
+
+/* Fills the caller's device array d_geometry (rk_deformed_geometry_bytes
+   bytes) for the map with amplitude eps (|eps| <= RK_MAX_DEFORM), computed
+   in fp64 and stored in dtype.  Asynchronous on hip_stream (NULL = default). */
+int rk_deformed_geometry(const rk_mesh* mesh, int degree, double eps, int dtype, void* d_geometry,
+                         void* hip_stream);
+
+/* v_s = h_alpha[s] M u_s + h_beta[s] K u_s for s < Q on [Q][N^3] device
+   vectors of dtype (the geometry must have the same dtype), with M and K the
+   deformed-mesh mass and stiffness matrices.  Cell-based sum factorisation:
+   each cell's geometry is read once and applied to all Q stages.  v is
+   overwritten; u and v must not overlap.  Asynchronous on hip_stream. */
+int rk_deformed_apply(const rk_mesh* mesh, int degree, int Q, const double* h_alpha, const double* h_beta,
+                      int dtype, const void* d_geometry, const void* d_u, void* d_v, void* hip_stream);
+
+/* Message of the last failed call on ctx (or of the last failed rk_create or
+   context-free call when ctx is NULL).  The pointer stays valid until the
+   next call. */
 const char* rk_last_error(const rk_ctx* ctx);
 
 #ifdef __cplusplus

@@ -149,10 +149,12 @@ class DeformedProblem:
         return np.asarray(v_full)[..., self.idx]
 
 
-def sampled_rows(n, k, eps, u_full, nodes):
+def sampled_rows(n, k, eps, u_full, nodes, absolute=False):
     """(M u)[node] and (K u)[node] for interior nodes (ix, iy, iz) of the full
     grid, from the element matrices of the cells around each node only (for
-    meshes too large to assemble).  u_full: boundary entries are ignored."""
+    meshes too large to assemble).  u_full: boundary entries are ignored.
+    With absolute, the entries of the element matrices enter by magnitude
+    (|M| u and |K| u, for rounding-error bounds)."""
     N = n * k + 1
     u = np.array(u_full, dtype=float).reshape(N, N, N)
     u[0], u[-1], u[:, 0], u[:, -1], u[:, :, 0], u[:, :, -1] = 0, 0, 0, 0, 0, 0
@@ -169,6 +171,8 @@ def sampled_rows(n, k, eps, u_full, nodes):
                         cells.append(cx + n * (cy + n * cz))
                         locs.append(a + n1 * (b + n1 * c))
         Me, Ke = element_matrices(n, k, eps, cells)
+        if absolute:
+            Me, Ke = np.abs(Me), np.abs(Ke)
         dofs = cell_dofs(n, k, cells)
         mv = sum(Me[e, locs[e]] @ u[dofs[e]] for e in range(len(cells)))
         kv = sum(Ke[e, locs[e]] @ u[dofs[e]] for e in range(len(cells)))

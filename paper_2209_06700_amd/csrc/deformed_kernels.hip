@@ -1,0 +1,363 @@
+// Cell-based operator on a deformed (non-affine) hexahedral mesh.
+//
+// The mesh is the uniform n^3 mesh of the unit cube mapped by
+//   Phi(x) = x + eps s(x) (1,1,1),  s(x) = sin(pi x1) sin(pi x2) sin(pi x3),
+// with Q_k elements on the reference cell (Gauss-Lobatto nodes) and the
+// (k+1)^3-point Gauss rule.  On such a mesh the element matrices differ from
+// cell to cell, so the operator evaluates cell integrals by sum factorisation
+// with per-point geometry: per Gauss point the mass factor m = w det J and the
+// symmetric stiffness metric G = w det J J^-1 J^-T (7 values).  Sec. 3.4
+// names this data as the reason to batch stages: the kernel loads a cell's
+// geometry once and applies it to all Q stages of the launch.
+//
+// Work decomposition: a workgroup owns CPW = 256 / (k+1)^2 cells of one
+// colour (cells whose index parity equals the colour bits), one thread per
+// (x, y) pencil of a cell; the z direction lives in registers, x and y pass
+// through LDS.  Cells of one colour share no node, so the eight colour
+// launches accumulate into the output without atomics and in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "element_data.h"
+#include "rk_internal.h"
+
+namespace rk {
+namespace {
+
+constexpr int kGeo = 7;   // m, Gxx, Gyy, Gzz, Gxy, Gxz, Gyz
+
+// Gauss point / weight q of degree K's rule (runtime q selects a constant)
+template <int K>
+__device__ __forceinline__ double gauss_x(int q) {
+    double r = 0.0;
+#pragma unroll
+    for (int t = 0; t <= K; ++t)
+        if (t == q) r = elem::Table<K>::d.gx[t];
+    return r;
+}
+template <int K>
+__device__ __forceinline__ double gauss_w(int q) {
+    double r = 0.0;
+#pragma unroll
+    for (int t = 0; t <= K; ++t)
+        if (t == q) r = elem::Table<K>::d.gw[t];
+    return r;
+}
+
+template <int K, typename T>
+__global__ void __launch_bounds__(256) geometry_kernel(T* __restrict__ geo, int n, double eps) {
+    constexpr int NQ = K + 1, NP = NQ * NQ * NQ;
+    const long long total = (long long)n * n * n * NP;
+    const double h = 1.0 / n, pi = 3.14159265358979323846;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        const long long cell = t / NP;
+        const int q = (int)(t - cell * NP);
+        const int qa = q % NQ, qb = (q / NQ) % NQ, qc = q / (NQ * NQ);
+        const int cx = (int)(cell % n), cy = (int)((cell / n) % n), cz = (int)(cell / ((long long)n * n));
+        double x[3] = {h * (cx + gauss_x<K>(qa)), h * (cy + gauss_x<K>(qb)), h * (cz + gauss_x<K>(qc))};
+        double sn[3], cs[3];
+        for (int d = 0; d < 3; ++d) { sn[d] = sin(pi * x[d]); cs[d] = cos(pi * x[d]); }
+        // grad s; Phi' = I + eps (1,1,1)^T grad s^T
+        const double g[3] = {pi * cs[0] * sn[1] * sn[2], pi * sn[0] * cs[1] * sn[2], pi * sn[0] * sn[1] * cs[2]};
+        const double a = 1.0 + eps * (g[0] + g[1] + g[2]);      // det Phi'
+        // Phi'^-1 = I - eps (1,1,1)^T grad s^T / a (Sherman-Morrison); J = h Phi'
+        double Ji[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Ji[r][c] = ((r == c ? 1.0 : 0.0) - eps * g[c] / a) / h;
+        const double w = gauss_w<K>(qa) * gauss_w<K>(qb) * gauss_w<K>(qc);
+        const double wdet = w * a * h * h * h;
+        double C[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) C[r][c] = Ji[r][0] * Ji[c][0] + Ji[r][1] * Ji[c][1] + Ji[r][2] * Ji[c][2];
+        T* o = geo + cell * (long long)(kGeo * NP) + q;
+        o[0 * NP] = T(wdet);
+        o[1 * NP] = T(wdet * C[0][0]);
+        o[2 * NP] = T(wdet * C[1][1]);
+        o[3 * NP] = T(wdet * C[2][2]);
+        o[4 * NP] = T(wdet * C[0][1]);
+        o[5 * NP] = T(wdet * C[0][2]);
+        o[6 * NP] = T(wdet * C[1][2]);
+    }
+}
+
+template <typename T>
+struct DefArgs {
+    const T* u;
+    T* v;
+    const T* geo;
+    long long stride;          // N^3
+    int n, nstage;
+    int bx, by, bz;            // colour bits
+    int ccx, ccy, ccz;         // cells of this colour per direction
+    long long ncell;           // ccx ccy ccz
+    T alpha[RK_MAX_Q], beta[RK_MAX_Q];
+};
+
+template <int K, typename T>
+__global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
+    constexpr auto& E = elem::Table<K>::d;
+    constexpr int NQ = K + 1, N2 = NQ * NQ, NP = N2 * NQ;
+    constexpr int CPW = 256 / N2;
+    __shared__ T bufA[CPW * NP];
+    __shared__ T bufB[CPW * NP];
+    const int tid = threadIdx.x;
+    const int lc = tid / N2;
+    const bool lane = lc < CPW;                      // owns an LDS slot
+    const int r = tid - lc * N2;
+    const int i = r % NQ, j = r / NQ;
+    const long long cid = (long long)blockIdx.x * CPW + lc;
+    const bool valid = lane && cid < p.ncell;
+    int cx = 0, cy = 0, cz = 0;
+    if (valid) {
+        cx = 2 * (int)(cid % p.ccx) + p.bx;
+        cy = 2 * (int)((cid / p.ccx) % p.ccy) + p.by;
+        cz = 2 * (int)(cid / ((long long)p.ccx * p.ccy)) + p.bz;
+    }
+    const int n = p.n, N = n * K + 1;
+    const long long NN = (long long)N * N;
+    T* A = bufA + (lane ? lc : 0) * NP;
+    T* B = bufB + (lane ? lc : 0) * NP;
+    // this pencil's geometry, loaded once for all stages
+    T gm[kGeo][NQ];
+    {
+        const long long cell = (long long)cx + (long long)n * (cy + (long long)n * cz);
+        const T* g = p.geo + cell * (long long)(kGeo * NP) + i + NQ * j;
+#pragma unroll
+        for (int c = 0; c < kGeo; ++c)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) gm[c][q] = valid ? g[c * NP + q * N2] : T(0);
+    }
+    // rows and columns of the 1D tables for this thread's x index i and y
+    // index j (runtime indices select among compile-time constants once)
+    T Bi[NQ], Bj[NQ], Di[NQ], Dj[NQ], BTi[NQ], BTj[NQ], DTi[NQ], DTj[NQ];
+#pragma unroll
+    for (int m = 0; m < NQ; ++m) {
+        Bi[m] = Bj[m] = Di[m] = Dj[m] = BTi[m] = BTj[m] = DTi[m] = DTj[m] = T(0);
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            if (t == i) {
+                Bi[m] = T(E.gB[t][m]); Di[m] = T(E.gD[t][m]);
+                BTi[m] = T(E.gB[m][t]); DTi[m] = T(E.gD[m][t]);
+            }
+            if (t == j) {
+                Bj[m] = T(E.gB[t][m]); Dj[m] = T(E.gD[t][m]);
+                BTj[m] = T(E.gB[m][t]); DTj[m] = T(E.gD[m][t]);
+            }
+        }
+    }
+    // node (cx K + i, cy K + j, cz K + l) of the pencil; interior test per node
+    const int gxn = cx * K + i, gyn = cy * K + j, gz0 = cz * K;
+    const bool col_in = valid && gxn > 0 && gxn < N - 1 && gyn > 0 && gyn < N - 1;
+    const long long colbase = (long long)gyn * N + gxn;
+    for (int s = 0; s < p.nstage; ++s) {
+        const T* us = p.u + (long long)s * p.stride;
+        T c[NQ];
+#pragma unroll
+        for (int l = 0; l < NQ; ++l) {
+            const int z = gz0 + l;
+            c[l] = (col_in && z > 0 && z < N - 1) ? us[colbase + z * NN] : T(0);
+        }
+        // values at the Gauss points: z in registers, then y and x through LDS
+        T t1[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            T acc = T(0);
+#pragma unroll
+            for (int a = 0; a < NQ; ++a) acc = fma(T(E.gB[q][a]), c[a], acc);
+            t1[q] = acc;
+        }
+        if (lane)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) A[q * N2 + j * NQ + i] = t1[q];
+        __syncthreads();
+        T t2[NQ];   // (x node i, y point j, z point q)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            T acc = T(0);
+            if (lane)
+#pragma unroll
+                for (int b = 0; b < NQ; ++b) acc = fma(Bj[b], A[q * N2 + b * NQ + i], acc);
+            t2[q] = acc;
+        }
+        if (lane)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) B[q * N2 + j * NQ + i] = t2[q];
+        __syncthreads();
+        T U[NQ];    // (x point i, y point j, z point q)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            T acc = T(0);
+            if (lane)
+#pragma unroll
+                for (int a = 0; a < NQ; ++a) acc = fma(Bi[a], B[q * N2 + j * NQ + a], acc);
+            U[q] = acc;
+        }
+        // reference gradients at the points (collocation derivative)
+        if (lane)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) A[q * N2 + j * NQ + i] = U[q];
+        __syncthreads();
+        T fx[NQ], fy[NQ], fz[NQ], W[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            T dz = T(0), dy = T(0), dx = T(0);
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) dz = fma(T(E.gD[q][m]), U[m], dz);
+            if (lane)
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) {
+                    dy = fma(Dj[m], A[q * N2 + m * NQ + i], dy);
+                    dx = fma(Di[m], A[q * N2 + j * NQ + m], dx);
+                }
+            const T al = p.alpha[s], be = p.beta[s];
+            W[q] = al * gm[0][q] * U[q];
+            fx[q] = be * (gm[1][q] * dx + gm[4][q] * dy + gm[5][q] * dz);
+            fy[q] = be * (gm[4][q] * dx + gm[2][q] * dy + gm[6][q] * dz);
+            fz[q] = be * (gm[5][q] * dx + gm[6][q] * dy + gm[3][q] * dz);
+        }
+        // transposed derivatives: z in registers, y and x through LDS
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            T acc = W[q];
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) acc = fma(T(E.gD[m][q]), fz[m], acc);
+            W[q] = acc;
+        }
+        if (lane)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) B[q * N2 + j * NQ + i] = fx[q];
+        __syncthreads();   // every thread has finished reading A (gradients)
+        if (lane)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) A[q * N2 + j * NQ + i] = fy[q];
+        __syncthreads();
+        if (lane)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T acc = W[q];
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) {
+                    acc = fma(DTj[m], A[q * N2 + m * NQ + i], acc);
+                    acc = fma(DTi[m], B[q * N2 + j * NQ + m], acc);
+                }
+                W[q] = acc;
+            }
+        __syncthreads();   // A and B free again
+        // back to the nodes: x and y through LDS, z in registers
+        if (lane)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) A[q * N2 + j * NQ + i] = W[q];
+        __syncthreads();
+        T r1[NQ];   // (x node i, y point j, z point q)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            T acc = T(0);
+            if (lane)
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) acc = fma(BTi[m], A[q * N2 + j * NQ + m], acc);
+            r1[q] = acc;
+        }
+        if (lane)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) B[q * N2 + j * NQ + i] = r1[q];
+        __syncthreads();
+        T r2[NQ];   // (x node i, y node j, z point q)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            T acc = T(0);
+            if (lane)
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) acc = fma(BTj[m], B[q * N2 + m * NQ + i], acc);
+            r2[q] = acc;
+        }
+        T* vs = p.v + (long long)s * p.stride;
+#pragma unroll
+        for (int l = 0; l < NQ; ++l) {
+            T acc = T(0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc = fma(T(E.gB[q][l]), r2[q], acc);
+            const int z = gz0 + l;
+            if (col_in && z > 0 && z < N - 1) vs[colbase + z * NN] += acc;
+        }
+    }
+}
+
+template <int K, typename T>
+hipError_t launch_typed(int n, int Q, const double* alpha, const double* beta, const void* geo,
+                        const void* u, void* v, hipStream_t st) {
+    constexpr int NQ = K + 1, N2 = NQ * NQ, CPW = 256 / N2;
+    const long long N = (long long)n * K + 1;
+    DefArgs<T> a;
+    a.u = static_cast<const T*>(u);
+    a.v = static_cast<T*>(v);
+    a.geo = static_cast<const T*>(geo);
+    a.stride = N * N * N;
+    a.n = n;
+    a.nstage = Q;
+    for (int s = 0; s < RK_MAX_Q; ++s) {
+        a.alpha[s] = T(s < Q ? alpha[s] : 0.0);
+        a.beta[s] = T(s < Q ? beta[s] : 0.0);
+    }
+    hipError_t e = launch_fill(sizeof(T) == 8 ? RK_FP64 : RK_FP32, v, (long long)Q * a.stride, 0.0, st);
+    if (e != hipSuccess) return e;
+    for (int colour = 0; colour < 8; ++colour) {
+        a.bx = colour & 1;
+        a.by = (colour >> 1) & 1;
+        a.bz = (colour >> 2) & 1;
+        a.ccx = (n - a.bx + 1) / 2;
+        a.ccy = (n - a.by + 1) / 2;
+        a.ccz = (n - a.bz + 1) / 2;
+        a.ncell = (long long)a.ccx * a.ccy * a.ccz;
+        if (a.ncell == 0) continue;
+        const long long blocks = (a.ncell + CPW - 1) / CPW;
+        deformed_op_kernel<K, T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int K, typename T>
+hipError_t geometry_typed(int n, double eps, void* geo, hipStream_t st) {
+    constexpr int NP = (K + 1) * (K + 1) * (K + 1);
+    const long long total = (long long)n * n * n * NP;
+    const long long blocks = std::min<long long>((total + 255) / 256, 1 << 20);
+    geometry_kernel<K, T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(static_cast<T*>(geo), n, eps);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t deformed_geometry_elems(int n, int k) {
+    return (size_t)n * n * n * kGeo * (size_t)(k + 1) * (k + 1) * (k + 1);
+}
+
+hipError_t launch_deformed_geometry(int k, int dtype, int n, double eps, void* geo, hipStream_t st) {
+#define RK_DEF_GEO(KK)                                                                         \
+    case KK:                                                                                   \
+        return dtype == RK_FP64 ? geometry_typed<KK, double>(n, eps, geo, st)                  \
+                                : geometry_typed<KK, float>(n, eps, geo, st);
+    switch (k) {
+        RK_DEF_GEO(1) RK_DEF_GEO(2) RK_DEF_GEO(3) RK_DEF_GEO(4) RK_DEF_GEO(5) RK_DEF_GEO(6)
+        default: return hipErrorInvalidValue;
+    }
+#undef RK_DEF_GEO
+}
+
+hipError_t launch_deformed_apply(int k, int dtype, int n, int Q, const double* alpha, const double* beta,
+                                 const void* geo, const void* u, void* v, hipStream_t st) {
+#define RK_DEF_OP(KK)                                                                          \
+    case KK:                                                                                   \
+        return dtype == RK_FP64 ? launch_typed<KK, double>(n, Q, alpha, beta, geo, u, v, st)   \
+                                : launch_typed<KK, float>(n, Q, alpha, beta, geo, u, v, st);
+    switch (k) {
+        RK_DEF_OP(1) RK_DEF_OP(2) RK_DEF_OP(3) RK_DEF_OP(4) RK_DEF_OP(5) RK_DEF_OP(6)
+        default: return hipErrorInvalidValue;
+    }
+#undef RK_DEF_OP
+}
+
+}  // namespace rk

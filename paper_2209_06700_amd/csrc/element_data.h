@@ -2,7 +2,11 @@
 // Gauss-Lobatto-Legendre nodes, the (K+1)-point Gauss rule, the element mass
 // and stiffness matrices  M[a][b] = int l_a l_b,  A[a][b] = int l_a' l_b'
 // (exact with K+1 Gauss points), and the prolongation from one cell to its two
-// halves  P[f][c] = l_c(x_f)  with fine nodes x/2 and 1/2 + x/2.
+// halves  P[f][c] = l_c(x_f)  with fine nodes x/2 and 1/2 + x/2.  For the
+// cell-based (deformed-mesh) operator also the basis values at the Gauss
+// points  gB[q][a] = l_a(g_q)  and the collocation derivative on the Gauss
+// points  gD[q][p] = L_p'(g_q)  (L_p the Lagrange polynomials on the Gauss
+// points), which maps values at the points to derivatives at the points.
 //
 // Everything is evaluated by the compiler in double (constexpr), so the device
 // kernels see the matrix entries as literal constants.  The host set-up uses
@@ -50,6 +54,8 @@ struct Data {
     double M[K + 1][K + 1];          // element mass matrix (unit cell)
     double A[K + 1][K + 1];          // element stiffness matrix (unit cell)
     double P[2 * K + 1][K + 1];      // cell-to-halves prolongation
+    double gB[K + 1][K + 1];         // GLL basis at the Gauss points, [q][a]
+    double gD[K + 1][K + 1];         // collocation derivative on the Gauss points, [q][p]
 };
 
 template <int K>
@@ -102,6 +108,18 @@ constexpr Data<K> make() {
             }
             B[q][a] = v;
             D[q][a] = dv;
+            d.gB[q][a] = v;
+        }
+    for (int q = 0; q < n; ++q)
+        for (int p = 0; p < n; ++p) {
+            double v = 1, dv = 0;
+            for (int m = 0; m < n; ++m) {
+                if (m == p) continue;
+                const double f = (d.gx[q] - d.gx[m]) / (d.gx[p] - d.gx[m]);
+                dv = dv * f + v / (d.gx[p] - d.gx[m]);
+                v *= f;
+            }
+            d.gD[q][p] = dv;
         }
     for (int a = 0; a <= K; ++a)
         for (int b = 0; b <= K; ++b) {

@@ -1076,6 +1076,55 @@ int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* cons
     return first;
 }
 
+// ---------------------------------------------------------------------------
+// Deformed-mesh operator (context-free).
+// ---------------------------------------------------------------------------
+namespace {
+int check_deformed(const rk_mesh* mesh, int degree, int dtype) {
+    if (!mesh || mesh->n_cells < 1 || degree < 1 || degree > RK_MAX_DEGREE)
+        return fail(nullptr, RK_EINVAL, "mesh or degree (1..6) out of range");
+    if ((long long)mesh->n_cells * degree + 1 > 16384)
+        return fail(nullptr, RK_EINVAL, "grid too large: need n_cells*degree + 1 <= 16384");
+    if (dtype != RK_FP64 && dtype != RK_FP32) return fail(nullptr, RK_EINVAL, "bad dtype");
+    return RK_OK;
+}
+}  // namespace
+
+int rk_deformed_geometry_bytes(const rk_mesh* mesh, int degree, int dtype, size_t* bytes) {
+    if (!bytes) return fail(nullptr, RK_EINVAL, "bytes is NULL");
+    int rc = check_deformed(mesh, degree, dtype);
+    if (rc) return rc;
+    *bytes = deformed_geometry_elems(mesh->n_cells, degree) * dsize(dtype);
+    return RK_OK;
+}
+
+int rk_deformed_geometry(const rk_mesh* mesh, int degree, double eps, int dtype, void* d_geometry,
+                         void* hip_stream) {
+    int rc = check_deformed(mesh, degree, dtype);
+    if (rc) return rc;
+    if (!d_geometry) return fail(nullptr, RK_EINVAL, "geometry is NULL");
+    if (!(std::fabs(eps) <= RK_MAX_DEFORM)) return fail(nullptr, RK_EINVAL, "|eps| must be <= RK_MAX_DEFORM");
+    hipError_t e = launch_deformed_geometry(degree, dtype, mesh->n_cells, eps, d_geometry, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(nullptr, RK_EHIP, std::string("deformed geometry: ") + hipGetErrorString(e));
+    return RK_OK;
+}
+
+int rk_deformed_apply(const rk_mesh* mesh, int degree, int Q, const double* alpha, const double* beta, int dtype,
+                      const void* d_geometry, const void* d_u, void* d_v, void* hip_stream) {
+    int rc = check_deformed(mesh, degree, dtype);
+    if (rc) return rc;
+    if (Q < 1 || Q > RK_MAX_Q) return fail(nullptr, RK_EINVAL, "Q out of range (1..9)");
+    if (!alpha || !beta || !d_geometry || !d_u || !d_v) return fail(nullptr, RK_EINVAL, "NULL argument");
+    const long long N = (long long)mesh->n_cells * degree + 1;
+    const size_t bytes = dsize(dtype) * (size_t)Q * N * N * N;
+    if ((const char*)d_u < (const char*)d_v + bytes && (const char*)d_v < (const char*)d_u + bytes)
+        return fail(nullptr, RK_EINVAL, "u and v overlap");
+    hipError_t e = launch_deformed_apply(degree, dtype, mesh->n_cells, Q, alpha, beta, d_geometry, d_u, d_v,
+                                         (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(nullptr, RK_EHIP, std::string("deformed apply: ") + hipGetErrorString(e));
+    return RK_OK;
+}
+
 const char* rk_last_error(const rk_ctx* c) {
     return c ? c->err.c_str() : g_create_error.c_str();
 }

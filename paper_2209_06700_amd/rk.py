@@ -19,7 +19,8 @@ from ._lib import (LIB, RK_BATCHED, RK_ENOCONV, RK_FP32, RK_FP64, RK_METHOD_COMP
 
 __all__ = ["RKError", "rk_default_options", "rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info",
            "rk_step", "rk_step_batch", "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner",
-           "rk_last_error",
+           "rk_last_error", "rk_deformed_geometry_bytes", "rk_deformed_geometry", "rk_deformed_apply",
+           "DeformedOperator",
            "RadauIIA", "RK_FP64", "RK_FP32", "RK_PREC_FP64", "RK_PREC_MIXED", "RK_BATCHED",
            "RK_PER_STAGE", "RK_OP_CALA", "RK_OP_STAGE", "RK_OP_BLOCKS", "RK_OP_K", "RK_OP_M",
            "RK_OP_CBLOCKS", "RK_METHOD_CROUT", "RK_METHOD_COMPLEX"]
@@ -226,6 +227,69 @@ def rk_apply_preconditioner(ctx: Context, r: torch.Tensor, z: torch.Tensor):
     n = ctx.Q * ctx.N ** 3
     _check(LIB.rk_apply_preconditioner(ctx.handle, _vec(r, n, "r", torch.float64),
                                        _vec(z, n, "z", torch.float64)), ctx)
+
+
+def _dtype_from_torch(dtype) -> int:
+    if dtype == torch.float64:
+        return RK_FP64
+    if dtype == torch.float32:
+        return RK_FP32
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def rk_deformed_geometry_bytes(n_cells: int, degree: int, dtype=torch.float64) -> int:
+    out = C.c_size_t(0)
+    _check(LIB.rk_deformed_geometry_bytes(C.byref(rk_mesh(n_cells)), degree, _dtype_from_torch(dtype),
+                                          C.byref(out)))
+    return out.value
+
+
+def rk_deformed_geometry(n_cells: int, degree: int, eps: float, geometry: torch.Tensor,
+                         stream: torch.cuda.Stream | None = None):
+    """Fill `geometry` (a CUDA tensor of the operator dtype and
+    rk_deformed_geometry_bytes bytes) for the map with amplitude eps."""
+    nbytes = rk_deformed_geometry_bytes(n_cells, degree, geometry.dtype)
+    if not geometry.is_cuda or not geometry.is_contiguous() or geometry.numel() * geometry.element_size() != nbytes:
+        raise ValueError(f"geometry must be a contiguous CUDA tensor of {nbytes} bytes")
+    st = stream if stream is not None else torch.cuda.current_stream(geometry.device)
+    _check(LIB.rk_deformed_geometry(C.byref(rk_mesh(n_cells)), degree, float(eps),
+                                    _dtype_from_torch(geometry.dtype), C.c_void_p(geometry.data_ptr()),
+                                    C.c_void_p(st.cuda_stream)))
+
+
+def rk_deformed_apply(n_cells: int, degree: int, alpha, beta, geometry: torch.Tensor, u: torch.Tensor,
+                      v: torch.Tensor, stream: torch.cuda.Stream | None = None):
+    """v_s = alpha[s] M u_s + beta[s] K u_s on the deformed mesh, Q = len(alpha)
+    stages of N^3 entries each; u, v, geometry of one dtype."""
+    Q = len(alpha)
+    if len(beta) != Q:
+        raise ValueError("alpha and beta need the same length")
+    N = n_cells * degree + 1
+    up = _vec(u, Q * N ** 3, "u")
+    vp = _vec(v, Q * N ** 3, "v", u.dtype)
+    if geometry.dtype != u.dtype or not geometry.is_cuda:
+        raise TypeError("geometry must be a CUDA tensor of the vectors' dtype")
+    st = stream if stream is not None else torch.cuda.current_stream(u.device)
+    a = (C.c_double * Q)(*[float(x) for x in alpha])
+    b = (C.c_double * Q)(*[float(x) for x in beta])
+    _check(LIB.rk_deformed_apply(C.byref(rk_mesh(n_cells)), degree, Q, a, b, _dtype_code(u),
+                                 C.c_void_p(geometry.data_ptr()), up, vp, C.c_void_p(st.cuda_stream)))
+
+
+class DeformedOperator:
+    """The deformed-mesh operator with its geometry array (torch-allocated)."""
+
+    def __init__(self, n_cells, degree, eps, dtype=torch.float64, device="cuda", stream=None):
+        self.n, self.k, self.eps, self.dtype = n_cells, degree, eps, dtype
+        self.N = n_cells * degree + 1
+        nbytes = rk_deformed_geometry_bytes(n_cells, degree, dtype)
+        esize = torch.tensor([], dtype=dtype).element_size()
+        self.geometry = torch.empty(nbytes // esize, dtype=dtype, device=device)
+        self.stream = stream
+        rk_deformed_geometry(n_cells, degree, eps, self.geometry, stream)
+
+    def apply(self, u, v, alpha, beta):
+        rk_deformed_apply(self.n, self.k, alpha, beta, self.geometry, u, v, self.stream)
 
 
 class RadauIIA:
