@@ -289,6 +289,40 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20):
             "fgmres_iterations": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
 
 
+def deformed_leg(torch, R, n=64, k=4, eps=0.05, qs=(1, 2, 4, 8), reps=10):
+    """The deformed-mesh operator (cell-based, per-point geometry) at n^3 Q_k
+    in fp32 for several stage counts: the geometry is read once per cell for
+    all Q stages, so its share of the traffic per stage-DoF falls as 1/Q."""
+    op = R.DeformedOperator(n, k, eps, dtype=torch.float32)
+    N = n * k + 1
+    geo_bytes = op.geometry.numel() * 4
+    nq = k + 1
+    flop_cell = 12 * 2 * nq ** 4 + 18 * nq ** 3        # 12 contractions + the point operation
+    out = {"mesh": f"{n}^3 cells Q_{k}, eps={eps}, fp32", "geometry_bytes": geo_bytes, "by_Q": {}}
+    for Q in qs:
+        u = torch.randn(Q * N ** 3, dtype=torch.float32, device="cuda")
+        v = torch.empty_like(u)
+        alpha, beta = [2.0] * Q, [5e-4] * Q
+        op.apply(u, v, alpha, beta)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            op.apply(u, v, alpha, beta)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        sd = Q * N ** 3
+        alg = 8.0 * sd + geo_bytes
+        out["by_Q"][str(Q)] = {"us_per_apply": t * 1e6, "stage_dofs_per_s": sd / t,
+                               "algorithmic_bytes_per_stage_dof": alg / sd, "GBps": alg / t / 1e9,
+                               "TFLOPs": flop_cell * n ** 3 * Q / t / 1e12}
+        del u, v
+    del op
+    torch.cuda.empty_cache()
+    return out
+
+
 def loosest_rtol(acc_runs, bound=1e-8):
     """The loosest FGMRES tolerance whose step error is within `bound`."""
     ok = [float(r) for r, v in acc_runs.items() if v["rel_l2_error"] <= bound]
@@ -304,6 +338,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host leg (oracle)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 per-stage comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven batch of 64 problems")
+    ap.add_argument("--no-deformed", action="store_true", help="skip the deformed-mesh operator leg")
     ap.add_argument("--no-complex", action="store_true",
                     help="skip the direct complex diagonalisation (PRESB) comparison")
     ap.add_argument("--n", type=int, default=64)
@@ -429,6 +464,11 @@ def main():
         batch = uneven_batch(torch, R)
         log(f"[bench] uneven batch of {batch['problems']}: {batch['s_concurrent'] * 1e3:.1f} ms concurrent, "
             f"{batch['s_sequential'] * 1e3:.1f} ms one after another")
+    deformed = None
+    if not args.no_deformed:
+        deformed = deformed_leg(torch, R, n=n, k=k)
+        log("[bench] deformed operator: " + ", ".join(
+            f"Q={q} {v['us_per_apply']:.0f} us ({v['stage_dofs_per_s']:.3g} sDoF/s)" for q, v in deformed["by_Q"].items()))
     flop = op_flops_per_stage_dof(k)
     achieved = flop * sdofs / t_blk / 1e12
     hbm_gbs = 8.0 * sdofs / t_blk / 1e9
@@ -457,6 +497,7 @@ def main():
             "ms_per_step": t_plain * 1e3, "fgmres_iterations": its_plain, "rtol": 1e-10,
             "speedup_of_mixed_batched": t_plain / t_step},
         "complex_presb": cx,
+        "deformed_operator": deformed,
         "at_1e-8_accuracy": at_acc,
         "uneven_batch": batch,
         "step_breakdown_s": {k2: breakdown[k2] for k2 in ("t_rhs", "t_vmult", "t_basis", "t_blocks", "t_rest")},

@@ -11,10 +11,9 @@
 // geometry once and applies it to all Q stages of the launch.
 //
 // Work decomposition: a workgroup owns CPW = 256 / (k+1)^2 cells of one
-// colour (cells whose index parity equals the colour bits), one thread per
-// (x, y) pencil of a cell; the z direction lives in registers, x and y pass
-// through LDS.  Cells of one colour share no node, so the eight colour
-// launches accumulate into the output without atomics and in a fixed order.
+// colour (cells whose index parity equals the colour bits), (k+1)^2 threads
+// per cell.  Cells of one colour share no node, so the eight colour launches
+// accumulate into the output without atomics and in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -96,18 +95,24 @@ struct DefArgs {
     T alpha[RK_MAX_Q], beta[RK_MAX_Q];
 };
 
+// Each one-dimensional contraction runs along pencils of its own direction:
+// the N2 = (k+1)^2 threads of a cell take the pencils along z (thread (a, b)
+// = (x, y)), along y ((a, b) = (x, z)) or along x ((a, b) = (y, z)), so every
+// coefficient of the 1D tables is a compile-time constant and a pass moves
+// k+1 values per thread through LDS.  Cell arrays in LDS are [z][y][x].
 template <int K, typename T>
 __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
     constexpr auto& E = elem::Table<K>::d;
     constexpr int NQ = K + 1, N2 = NQ * NQ, NP = N2 * NQ;
     constexpr int CPW = 256 / N2;
-    __shared__ T bufA[CPW * NP];
-    __shared__ T bufB[CPW * NP];
+    __shared__ T L0[CPW * NP];
+    __shared__ T L1[CPW * NP];
+    __shared__ T L2[CPW * NP];
     const int tid = threadIdx.x;
     const int lc = tid / N2;
     const bool lane = lc < CPW;                      // owns an LDS slot
     const int r = tid - lc * N2;
-    const int i = r % NQ, j = r / NQ;
+    const int a = r % NQ, b = r / NQ;
     const long long cid = (long long)blockIdx.x * CPW + lc;
     const bool valid = lane && cid < p.ncell;
     int cx = 0, cy = 0, cz = 0;
@@ -118,169 +123,169 @@ __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
     }
     const int n = p.n, N = n * K + 1;
     const long long NN = (long long)N * N;
-    T* A = bufA + (lane ? lc : 0) * NP;
-    T* B = bufB + (lane ? lc : 0) * NP;
-    // this pencil's geometry, loaded once for all stages
+    T* A = L0 + (lane ? lc : 0) * NP;
+    T* B = L1 + (lane ? lc : 0) * NP;
+    T* C = L2 + (lane ? lc : 0) * NP;
+    const int zb = a + NQ * b;          // z pencil (x = a, y = b): element zb + N2 l
+    const int yb = a + N2 * b;          // y pencil (x = a, z = b): element yb + NQ m
+    const int xb = NQ * a + N2 * b;     // x pencil (y = a, z = b): element xb + m
+    // geometry of this thread's z pencil of points, loaded once for all stages
     T gm[kGeo][NQ];
     {
         const long long cell = (long long)cx + (long long)n * (cy + (long long)n * cz);
-        const T* g = p.geo + cell * (long long)(kGeo * NP) + i + NQ * j;
+        const T* g = p.geo + cell * (long long)(kGeo * NP) + zb;
 #pragma unroll
         for (int c = 0; c < kGeo; ++c)
 #pragma unroll
             for (int q = 0; q < NQ; ++q) gm[c][q] = valid ? g[c * NP + q * N2] : T(0);
     }
-    // rows and columns of the 1D tables for this thread's x index i and y
-    // index j (runtime indices select among compile-time constants once)
-    T Bi[NQ], Bj[NQ], Di[NQ], Dj[NQ], BTi[NQ], BTj[NQ], DTi[NQ], DTj[NQ];
-#pragma unroll
-    for (int m = 0; m < NQ; ++m) {
-        Bi[m] = Bj[m] = Di[m] = Dj[m] = BTi[m] = BTj[m] = DTi[m] = DTj[m] = T(0);
-#pragma unroll
-        for (int t = 0; t < NQ; ++t) {
-            if (t == i) {
-                Bi[m] = T(E.gB[t][m]); Di[m] = T(E.gD[t][m]);
-                BTi[m] = T(E.gB[m][t]); DTi[m] = T(E.gD[m][t]);
-            }
-            if (t == j) {
-                Bj[m] = T(E.gB[t][m]); Dj[m] = T(E.gD[t][m]);
-                BTj[m] = T(E.gB[m][t]); DTj[m] = T(E.gD[m][t]);
-            }
-        }
-    }
-    // node (cx K + i, cy K + j, cz K + l) of the pencil; interior test per node
-    const int gxn = cx * K + i, gyn = cy * K + j, gz0 = cz * K;
+    // node (cx K + a, cy K + b, cz K + l) of the z pencil
+    const int gxn = cx * K + a, gyn = cy * K + b, gz0 = cz * K;
     const bool col_in = valid && gxn > 0 && gxn < N - 1 && gyn > 0 && gyn < N - 1;
     const long long colbase = (long long)gyn * N + gxn;
     for (int s = 0; s < p.nstage; ++s) {
         const T* us = p.u + (long long)s * p.stride;
-        T c[NQ];
+        T v[NQ], w[NQ];
 #pragma unroll
         for (int l = 0; l < NQ; ++l) {
             const int z = gz0 + l;
-            c[l] = (col_in && z > 0 && z < N - 1) ? us[colbase + z * NN] : T(0);
+            v[l] = (col_in && z > 0 && z < N - 1) ? us[colbase + z * NN] : T(0);
         }
-        // values at the Gauss points: z in registers, then y and x through LDS
-        T t1[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            T acc = T(0);
-#pragma unroll
-            for (int a = 0; a < NQ; ++a) acc = fma(T(E.gB[q][a]), c[a], acc);
-            t1[q] = acc;
-        }
-        if (lane)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) A[q * N2 + j * NQ + i] = t1[q];
-        __syncthreads();
-        T t2[NQ];   // (x node i, y point j, z point q)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            T acc = T(0);
-            if (lane)
-#pragma unroll
-                for (int b = 0; b < NQ; ++b) acc = fma(Bj[b], A[q * N2 + b * NQ + i], acc);
-            t2[q] = acc;
-        }
-        if (lane)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) B[q * N2 + j * NQ + i] = t2[q];
-        __syncthreads();
-        T U[NQ];    // (x point i, y point j, z point q)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            T acc = T(0);
-            if (lane)
-#pragma unroll
-                for (int a = 0; a < NQ; ++a) acc = fma(Bi[a], B[q * N2 + j * NQ + a], acc);
-            U[q] = acc;
-        }
-        // reference gradients at the points (collocation derivative)
-        if (lane)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) A[q * N2 + j * NQ + i] = U[q];
-        __syncthreads();
-        T fx[NQ], fy[NQ], fz[NQ], W[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            T dz = T(0), dy = T(0), dx = T(0);
-#pragma unroll
-            for (int m = 0; m < NQ; ++m) dz = fma(T(E.gD[q][m]), U[m], dz);
-            if (lane)
-#pragma unroll
-                for (int m = 0; m < NQ; ++m) {
-                    dy = fma(Dj[m], A[q * N2 + m * NQ + i], dy);
-                    dx = fma(Di[m], A[q * N2 + j * NQ + m], dx);
-                }
-            const T al = p.alpha[s], be = p.beta[s];
-            W[q] = al * gm[0][q] * U[q];
-            fx[q] = be * (gm[1][q] * dx + gm[4][q] * dy + gm[5][q] * dz);
-            fy[q] = be * (gm[4][q] * dx + gm[2][q] * dy + gm[6][q] * dz);
-            fz[q] = be * (gm[5][q] * dx + gm[6][q] * dy + gm[3][q] * dz);
-        }
-        // transposed derivatives: z in registers, y and x through LDS
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            T acc = W[q];
-#pragma unroll
-            for (int m = 0; m < NQ; ++m) acc = fma(T(E.gD[m][q]), fz[m], acc);
-            W[q] = acc;
-        }
-        if (lane)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) B[q * N2 + j * NQ + i] = fx[q];
-        __syncthreads();   // every thread has finished reading A (gradients)
-        if (lane)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) A[q * N2 + j * NQ + i] = fy[q];
-        __syncthreads();
+        // values at the Gauss points: z, y, x
         if (lane)
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                T acc = W[q];
+                T acc = T(0);
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) acc = fma(T(E.gB[q][m]), v[m], acc);
+                A[zb + N2 * q] = acc;
+            }
+        __syncthreads();
+        if (lane) {
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) v[m] = A[yb + NQ * m];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T acc = T(0);
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) acc = fma(T(E.gB[q][m]), v[m], acc);
+                B[yb + NQ * q] = acc;
+            }
+        }
+        __syncthreads();
+        if (lane) {
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) v[m] = B[xb + m];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T acc = T(0);
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) acc = fma(T(E.gB[q][m]), v[m], acc);
+                A[xb + q] = acc;
+            }
+        }
+        __syncthreads();
+        // reference derivatives along y (into B) and x (into C), collocation
+        if (lane) {
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) { v[m] = A[yb + NQ * m]; w[m] = A[xb + m]; }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T dy = T(0), dx = T(0);
 #pragma unroll
                 for (int m = 0; m < NQ; ++m) {
-                    acc = fma(DTj[m], A[q * N2 + m * NQ + i], acc);
-                    acc = fma(DTi[m], B[q * N2 + j * NQ + m], acc);
+                    dy = fma(T(E.gD[q][m]), v[m], dy);
+                    dx = fma(T(E.gD[q][m]), w[m], dx);
                 }
-                W[q] = acc;
+                B[yb + NQ * q] = dy;
+                C[xb + q] = dx;
             }
-        __syncthreads();   // A and B free again
-        // back to the nodes: x and y through LDS, z in registers
-        if (lane)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) A[q * N2 + j * NQ + i] = W[q];
-        __syncthreads();
-        T r1[NQ];   // (x node i, y point j, z point q)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            T acc = T(0);
-            if (lane)
-#pragma unroll
-                for (int m = 0; m < NQ; ++m) acc = fma(BTi[m], A[q * N2 + j * NQ + m], acc);
-            r1[q] = acc;
         }
-        if (lane)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) B[q * N2 + j * NQ + i] = r1[q];
         __syncthreads();
-        T r2[NQ];   // (x node i, y node j, z point q)
+        // the point operation on z pencils, with the z derivative and its
+        // transpose in registers
+        if (lane) {
+            T U[NQ], dy[NQ], dx[NQ], fz[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            T acc = T(0);
-            if (lane)
+            for (int q = 0; q < NQ; ++q) { U[q] = A[zb + N2 * q]; dy[q] = B[zb + N2 * q]; dx[q] = C[zb + N2 * q]; }
+            const T al = p.alpha[s], be = p.beta[s];
 #pragma unroll
-                for (int m = 0; m < NQ; ++m) acc = fma(BTj[m], B[q * N2 + m * NQ + i], acc);
-            r2[q] = acc;
+            for (int q = 0; q < NQ; ++q) {
+                T dz = T(0);
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) dz = fma(T(E.gD[q][m]), U[m], dz);
+                v[q] = al * gm[0][q] * U[q];
+                const T fx = be * (gm[1][q] * dx[q] + gm[4][q] * dy[q] + gm[5][q] * dz);
+                const T fy = be * (gm[4][q] * dx[q] + gm[2][q] * dy[q] + gm[6][q] * dz);
+                fz[q] = be * (gm[5][q] * dx[q] + gm[6][q] * dy[q] + gm[3][q] * dz);
+                B[zb + N2 * q] = fy;
+                C[zb + N2 * q] = fx;
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T acc = v[q];
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) acc = fma(T(E.gD[m][q]), fz[m], acc);
+                A[zb + N2 * q] = acc;
+            }
         }
+        __syncthreads();
+        // transposed y derivative, added on y pencils
+        if (lane) {
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) v[m] = B[yb + NQ * m];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T acc = A[yb + NQ * q];
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) acc = fma(T(E.gD[m][q]), v[m], acc);
+                A[yb + NQ * q] = acc;
+            }
+        }
+        __syncthreads();
+        // transposed x derivative, then back to the x nodes, on x pencils
+        if (lane) {
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) { v[m] = C[xb + m]; w[m] = A[xb + m]; }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) w[q] = fma(T(E.gD[m][q]), v[m], w[q]);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                T acc = T(0);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) acc = fma(T(E.gB[q][i]), w[q], acc);
+                B[xb + i] = acc;
+            }
+        }
+        __syncthreads();
+        // back to the y nodes on y pencils
+        if (lane) {
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) v[m] = B[yb + NQ * m];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) {
+                T acc = T(0);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) acc = fma(T(E.gB[q][j]), v[q], acc);
+                C[yb + NQ * j] = acc;
+            }
+        }
+        __syncthreads();
+        // back to the z nodes on z pencils, accumulated into v
         T* vs = p.v + (long long)s * p.stride;
+        if (lane) {
 #pragma unroll
-        for (int l = 0; l < NQ; ++l) {
-            T acc = T(0);
+            for (int q = 0; q < NQ; ++q) w[q] = C[zb + N2 * q];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) acc = fma(T(E.gB[q][l]), r2[q], acc);
-            const int z = gz0 + l;
-            if (col_in && z > 0 && z < N - 1) vs[colbase + z * NN] += acc;
+            for (int l = 0; l < NQ; ++l) {
+                T acc = T(0);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) acc = fma(T(E.gB[q][l]), w[q], acc);
+                const int z = gz0 + l;
+                if (col_in && z > 0 && z < N - 1) vs[colbase + z * NN] += acc;
+            }
         }
     }
 }
