@@ -127,6 +127,10 @@ typedef struct {
                                    coarse), used as given; NULL = estimate at create */
     int32_t timing;             /* 1: fill the per-component times of rk_stats     */
     int32_t method;             /* RK_METHOD_CROUT | RK_METHOD_COMPLEX              */
+    double  deform;             /* 0: the affine mesh.  Otherwise the Krylov operator
+                                   and K y_n live on the deformed mesh with this eps
+                                   (|eps| <= RK_MAX_DEFORM, see rk_deformed_apply);
+                                   the preconditioner keeps the affine-mesh V-cycles */
 } rk_options;
 
 typedef struct {
@@ -162,7 +166,7 @@ typedef struct {
 /* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
    max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
    cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0,
-   RK_METHOD_CROUT. */
+   RK_METHOD_CROUT, deform 0. */
 void rk_default_options(rk_options* opt);
 
 /* Bytes of device workspace needed for the given mesh, degree (1..6),
@@ -218,7 +222,9 @@ int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* cons
 
 /* v = op(u) for one of the RK_OP_* forms, with dtype RK_FP64 or RK_FP32 for
    both vectors.  Q-stage forms take [Q][N^3] vectors, RK_OP_K / RK_OP_M one
-   [N^3] vector.  u and v must not overlap.  Asynchronous. */
+   [N^3] vector.  u and v must not overlap.  Asynchronous.  A context with
+   deform != 0 applies RK_OP_CALA, RK_OP_CBLOCKS, RK_OP_K and RK_OP_M on the
+   deformed mesh, in fp64 only; other forms return RK_EINVAL there. */
 int rk_apply_operator(rk_ctx* ctx, int form, int dtype, const void* d_u, void* d_v);
 
 /* x_i = one V-cycle for the block lam_i M + tau K applied to b_i, i = 1..Q,

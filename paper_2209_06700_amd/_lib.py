@@ -38,7 +38,8 @@ class rk_options(C.Structure):
                 ("max_iter", C.c_int32), ("restart", C.c_int32), ("cheb_degree", C.c_int32),
                 ("coarse_cheb_degree", C.c_int32), ("cheb_range", C.c_double),
                 ("eig_safety", C.c_double), ("eig_iterations", C.c_int32),
-                ("eig_max", C.POINTER(C.c_double)), ("timing", C.c_int32), ("method", C.c_int32)]
+                ("eig_max", C.POINTER(C.c_double)), ("timing", C.c_int32), ("method", C.c_int32),
+                ("deform", C.c_double)]
 
 
 class rk_stats(C.Structure):

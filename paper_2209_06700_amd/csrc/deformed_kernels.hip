@@ -84,7 +84,8 @@ __global__ void __launch_bounds__(256) geometry_kernel(T* __restrict__ geo, int 
 
 template <typename T>
 struct DefArgs {
-    const T* u;
+    const T* u;                // stiffness-term input (and mass-term input unless PAIR)
+    const T* um;               // PAIR: mass-term input
     T* v;
     const T* geo;
     long long stride;          // N^3
@@ -100,7 +101,9 @@ struct DefArgs {
 // = (x, y)), along y ((a, b) = (x, z)) or along x ((a, b) = (y, z)), so every
 // coefficient of the 1D tables is a compile-time constant and a pass moves
 // k+1 values per thread through LDS.  Cell arrays in LDS are [z][y][x].
-template <int K, typename T>
+// PAIR: v_s = alpha_s M um_s + beta_s K u_s (two inputs, as in the stage
+// operator of eq. irk:A with a pre-mixed mass-term input).
+template <int K, typename T, bool PAIR>
 __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
     constexpr auto& E = elem::Table<K>::d;
     constexpr int NQ = K + 1, N2 = NQ * NQ, NP = N2 * NQ;
@@ -144,8 +147,55 @@ __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
     const bool col_in = valid && gxn > 0 && gxn < N - 1 && gyn > 0 && gyn < N - 1;
     const long long colbase = (long long)gyn * N + gxn;
     for (int s = 0; s < p.nstage; ++s) {
-        const T* us = p.u + (long long)s * p.stride;
         T v[NQ], w[NQ];
+        T UM[NQ];   // PAIR: the mass-term input at this z pencil of points
+        if constexpr (PAIR) {
+            const T* ums = p.um + (long long)s * p.stride;
+#pragma unroll
+            for (int l = 0; l < NQ; ++l) {
+                const int z = gz0 + l;
+                v[l] = (col_in && z > 0 && z < N - 1) ? ums[colbase + z * NN] : T(0);
+            }
+            if (lane)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int m = 0; m < NQ; ++m) acc = fma(T(E.gB[q][m]), v[m], acc);
+                    A[zb + N2 * q] = acc;
+                }
+            __syncthreads();
+            if (lane) {
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) v[m] = A[yb + NQ * m];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int m = 0; m < NQ; ++m) acc = fma(T(E.gB[q][m]), v[m], acc);
+                    B[yb + NQ * q] = acc;
+                }
+            }
+            __syncthreads();
+            if (lane) {
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) v[m] = B[xb + m];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int m = 0; m < NQ; ++m) acc = fma(T(E.gB[q][m]), v[m], acc);
+                    C[xb + q] = acc;
+                }
+            }
+            __syncthreads();
+            if (lane)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) UM[q] = C[zb + N2 * q];
+            // A, B are free (their reads are behind the last barrier); C is
+            // rewritten only after the next two barriers
+        }
+        const T* us = p.u + (long long)s * p.stride;
 #pragma unroll
         for (int l = 0; l < NQ; ++l) {
             const int z = gz0 + l;
@@ -214,7 +264,7 @@ __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
                 T dz = T(0);
 #pragma unroll
                 for (int m = 0; m < NQ; ++m) dz = fma(T(E.gD[q][m]), U[m], dz);
-                v[q] = al * gm[0][q] * U[q];
+                v[q] = al * gm[0][q] * (PAIR ? UM[q] : U[q]);
                 const T fx = be * (gm[1][q] * dx[q] + gm[4][q] * dy[q] + gm[5][q] * dz);
                 const T fy = be * (gm[4][q] * dx[q] + gm[2][q] * dy[q] + gm[6][q] * dz);
                 fz[q] = be * (gm[5][q] * dx[q] + gm[6][q] * dy[q] + gm[3][q] * dz);
@@ -292,11 +342,12 @@ __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
 
 template <int K, typename T>
 hipError_t launch_typed(int n, int Q, const double* alpha, const double* beta, const void* geo,
-                        const void* u, void* v, hipStream_t st) {
+                        const void* um, const void* u, void* v, hipStream_t st) {
     constexpr int NQ = K + 1, N2 = NQ * NQ, CPW = 256 / N2;
     const long long N = (long long)n * K + 1;
     DefArgs<T> a;
     a.u = static_cast<const T*>(u);
+    a.um = static_cast<const T*>(um);
     a.v = static_cast<T*>(v);
     a.geo = static_cast<const T*>(geo);
     a.stride = N * N * N;
@@ -318,7 +369,8 @@ hipError_t launch_typed(int n, int Q, const double* alpha, const double* beta, c
         a.ncell = (long long)a.ccx * a.ccy * a.ccz;
         if (a.ncell == 0) continue;
         const long long blocks = (a.ncell + CPW - 1) / CPW;
-        deformed_op_kernel<K, T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
+        if (um != u) deformed_op_kernel<K, T, true><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
+        else deformed_op_kernel<K, T, false><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -353,11 +405,11 @@ hipError_t launch_deformed_geometry(int k, int dtype, int n, double eps, void* g
 }
 
 hipError_t launch_deformed_apply(int k, int dtype, int n, int Q, const double* alpha, const double* beta,
-                                 const void* geo, const void* u, void* v, hipStream_t st) {
-#define RK_DEF_OP(KK)                                                                          \
-    case KK:                                                                                   \
-        return dtype == RK_FP64 ? launch_typed<KK, double>(n, Q, alpha, beta, geo, u, v, st)   \
-                                : launch_typed<KK, float>(n, Q, alpha, beta, geo, u, v, st);
+                                 const void* geo, const void* um, const void* u, void* v, hipStream_t st) {
+#define RK_DEF_OP(KK)                                                                              \
+    case KK:                                                                                       \
+        return dtype == RK_FP64 ? launch_typed<KK, double>(n, Q, alpha, beta, geo, um, u, v, st)   \
+                                : launch_typed<KK, float>(n, Q, alpha, beta, geo, um, u, v, st);
     switch (k) {
         RK_DEF_OP(1) RK_DEF_OP(2) RK_DEF_OP(3) RK_DEF_OP(4) RK_DEF_OP(5) RK_DEF_OP(6)
         default: return hipErrorInvalidValue;

@@ -433,6 +433,14 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(T* __restrict__ x, long lo
         x[i] = value;
 }
 
+// v = b - v
+__global__ void __launch_bounds__(kBlock) sub_from_kernel(double* __restrict__ v, const double* __restrict__ b,
+                                                          long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        v[i] = b[i] - v[i];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) copy_kernel(const T* __restrict__ src, T* __restrict__ dst, long long n) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -655,6 +663,11 @@ hipError_t launch_stage_combine(double* y, const double* kv, const double* b, do
 hipError_t launch_fill(int dtype, void* x, long long n, double value, hipStream_t st) {
     if (dtype == RK_FP64) fill_kernel<double><<<grid_for(n), kBlock, 0, st>>>((double*)x, n, value);
     else fill_kernel<float><<<grid_for(n), kBlock, 0, st>>>((float*)x, n, (float)value);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_from(double* v, const double* b, long long n, hipStream_t st) {
+    sub_from_kernel<<<grid_for(n), kBlock, 0, st>>>(v, b, n);
     return hipGetLastError();
 }
 

@@ -112,6 +112,8 @@ struct rk_ctx {
     int vc_graph = 0;              // 0 not tried, 1 captured, -1 eager only
     int pc = RK_FP64;              // preconditioner dtype
     bool cplx = false;             // direct diagonalisation with PRESB
+    bool deformed = false;         // Krylov operator and K y_n on the deformed mesh
+    void* geo = nullptr;           // its per-point geometry (fp64)
     int ng = 1;                    // independent Krylov systems (complex: the nb blocks)
     Segs seg;                      // their segments of the Krylov vectors
     SlotIdx slot_group;            // slot -> group
@@ -171,6 +173,7 @@ bool valid_options(const rk_options& o, std::string& msg) {
     }
     if (!(o.cheb_range > 1.0) || !(o.eig_safety > 0.0) || o.eig_iterations < 1) { msg = "bad Chebyshev interval settings"; return false; }
     if (o.method != RK_METHOD_CROUT && o.method != RK_METHOD_COMPLEX) { msg = "bad method"; return false; }
+    if (!(std::fabs(o.deform) <= RK_MAX_DEFORM)) { msg = "|deform| must be <= RK_MAX_DEFORM"; return false; }
     return true;
 }
 
@@ -246,6 +249,7 @@ size_t carve(rk_ctx& c, char* base) {
     c.sig = (double*)cv.take(8 * (size_t)(m + 16) * kSigStride);
     c.mix = (double*)cv.take(8 * kMixSlots * 81);
     c.mbuf = cv.take(8 * (size_t)qn);
+    if (c.deformed) c.geo = cv.take(8 * deformed_geometry_elems(c.n, c.k));
     return cv.off + kAlign;
 }
 
@@ -269,6 +273,7 @@ int setup_sizes(rk_ctx& c, const rk_mesh* mesh, int degree, int Q, const rk_opti
     c.h = 1.0 / c.n;
     c.pc = c.opt.precision == RK_PREC_MIXED ? RK_FP32 : RK_FP64;
     c.cplx = c.opt.method == RK_METHOD_COMPLEX;
+    c.deformed = c.opt.deform != 0.0;
     c.lv.clear();
     for (int m : level_cells(c.n)) {
         Level L;
@@ -630,10 +635,25 @@ int group_norm2(rk_ctx* c, const double* x, double* out, double* inv_sqrt = null
     return RK_OK;
 }
 
+// v_s = alpha_s M um_s + beta_s K u_s on the deformed mesh (fp64, ns stages).
+int deformed_op(rk_ctx* c, int ns, const double* alpha, const double* beta, const void* um, const void* u,
+                void* v) {
+    HIPCHK(c, launch_deformed_apply(c->k, RK_FP64, c->n, ns, alpha, beta, c->geo, um, u, v, c->stream));
+    return RK_OK;
+}
+
 // v = (D (x) M + tau I (x) K) u given m = (D (x) I) u, where D = A^-1 (eq.
 // irk:A, Crout method) or Lam_r (complex method); with b, v = b - (...) u.
 int apply_krylov(rk_ctx* c, const double* u, const double* m, double* v, const double* b) {
     Timer t(c, C_VMULT);
+    if (c->deformed) {
+        double al[RK_MAX_Q], be[RK_MAX_Q];
+        for (int s = 0; s < c->Q; ++s) { al[s] = 1.0; be[s] = c->tau; }
+        int rc = deformed_op(c, c->Q, al, be, m, u, v);
+        if (rc || !b) return rc;
+        HIPCHK(c, launch_sub_from(v, b, (long long)c->Q * c->N3, c->stream));
+        return RK_OK;
+    }
     return op(c, c->k, RK_FP64, b ? EPI_RESID : EPI_STORE, c->form[c->cplx ? F_CBLK : F_CALA], m, v, b, nullptr,
               c->n, 0, c->Q, 0, 0, u);
 }
@@ -798,6 +818,7 @@ void rk_default_options(rk_options* o) {
     o->eig_max = nullptr;
     o->timing = 0;
     o->method = RK_METHOD_CROUT;
+    o->deform = 0.0;
 }
 
 int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {
@@ -898,6 +919,8 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
             }
     }
     hipError_t e = hipMemcpyAsync(c->mix, mix.data(), mix.size() * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && c->deformed)
+        e = launch_deformed_geometry(c->k, RK_FP64, c->n, c->opt.deform, c->geo, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { delete c; return fail(nullptr, RK_EHIP, hipGetErrorString(e)); }
     if (!c->eig_user.empty()) {
@@ -950,6 +973,21 @@ int rk_apply_operator(rk_ctx* c, int form, int dtype, const void* u, void* v) {
     if ((const char*)u < (const char*)v + bytes && (const char*)v < (const char*)u + bytes)
         return fail(c, RK_EINVAL, "u and v overlap");
     const Coeffs& cf = c->form[form];
+    if (c->deformed) {
+        if (dtype != RK_FP64) return fail(c, RK_EINVAL, "a deformed-mesh context applies fp64 operators only");
+        double al[RK_MAX_Q], be[RK_MAX_Q];
+        if (form == F_K || form == F_M) {
+            al[0] = form == F_M ? 1.0 : 0.0;
+            be[0] = form == F_K ? 1.0 : 0.0;
+            return deformed_op(c, 1, al, be, u, u, v);
+        }
+        if (form != F_CALA && form != F_CBLK)
+            return fail(c, RK_EINVAL, "operator form not available on a deformed mesh");
+        HIPCHK(c, launch_stage_mix(RK_FP64, u, RK_FP64, c->mbuf, c->mix + (form == F_CALA ? kMixAinv : kMixCLam),
+                                   c->Q, c->Q, c->N, c->stream));
+        for (int s = 0; s < c->Q; ++s) { al[s] = 1.0; be[s] = c->tau; }
+        return deformed_op(c, c->Q, al, be, c->mbuf, u, v);
+    }
     if (!cf.pair) return op(c, c->k, dtype, EPI_STORE, cf, u, v, nullptr, nullptr, c->n, 0, ns, 0, 0);
     // dense forms: mix the input once, then the pair operator
     const double* D = c->mix + (cf.premix == 1 ? kMixAinv : cf.premix == 2 ? kMixA : kMixCLam);
@@ -988,7 +1026,12 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
     // for the complex method directly in slots, (T (x) I) rhs.
     {
         Timer t(c, C_RHS);
-        rc = op(c, c->k, RK_FP64, EPI_STORE, c->form[F_K], y, c->Ky, nullptr, nullptr, c->n, 0, 1, 0, 0);
+        if (c->deformed) {
+            const double al = 0.0, be = 1.0;
+            rc = deformed_op(c, 1, &al, &be, y, y, c->Ky);
+        } else {
+            rc = op(c, c->k, RK_FP64, EPI_STORE, c->form[F_K], y, c->Ky, nullptr, nullptr, c->n, 0, 1, 0, 0);
+        }
         if (rc) return rc;
         double c1[RK_MAX_Q], c2[RK_MAX_Q], cf[2 * RK_MAX_Q];
         for (int i = 0; i < Q; ++i) {
@@ -1119,7 +1162,7 @@ int rk_deformed_apply(const rk_mesh* mesh, int degree, int Q, const double* alph
     const size_t bytes = dsize(dtype) * (size_t)Q * N * N * N;
     if ((const char*)d_u < (const char*)d_v + bytes && (const char*)d_v < (const char*)d_u + bytes)
         return fail(nullptr, RK_EINVAL, "u and v overlap");
-    hipError_t e = launch_deformed_apply(degree, dtype, mesh->n_cells, Q, alpha, beta, d_geometry, d_u, d_v,
+    hipError_t e = launch_deformed_apply(degree, dtype, mesh->n_cells, Q, alpha, beta, d_geometry, d_u, d_u, d_v,
                                          (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(nullptr, RK_EHIP, std::string("deformed apply: ") + hipGetErrorString(e));
     return RK_OK;

@@ -170,6 +170,8 @@ hipError_t launch_stage_combine(double* y, const double* kv, const double* b, do
                                 int N, hipStream_t st);
 hipError_t launch_fill(int dtype, void* x, long long n, double value, hipStream_t st);
 hipError_t launch_copy(int dtype, const void* src, void* dst, long long n, hipStream_t st);
+// v = b - v (fp64)
+hipError_t launch_sub_from(double* v, const double* b, long long n, hipStream_t st);
 
 // Deformed-mesh operator (deformed_kernels.hip).  Geometry: per cell and
 // Gauss point the 7 values m = w det J, G = w det J J^-1 J^-T (xx, yy, zz, xy,
@@ -177,11 +179,12 @@ hipError_t launch_copy(int dtype, const void* src, void* dst, long long n, hipSt
 // stored [cell][7][point] (cells x fastest, points x fastest); element count
 // from deformed_geometry_elems.  Apply: v_s = alpha_s M u_s + beta_s K u_s for
 // s < Q on [Q][N^3] vectors (boundary entries read as 0, written 0); v is
-// overwritten.  alpha, beta: host arrays of Q values.
+// overwritten.  With um != u the mass term takes um: v_s = alpha_s M um_s +
+// beta_s K u_s.  alpha, beta: host arrays of Q values.
 size_t deformed_geometry_elems(int n, int k);
 hipError_t launch_deformed_geometry(int k, int dtype, int n, double eps, void* geo, hipStream_t st);
 hipError_t launch_deformed_apply(int k, int dtype, int n, int Q, const double* alpha, const double* beta,
-                                 const void* geo, const void* u, void* v, hipStream_t st);
+                                 const void* geo, const void* um, const void* u, void* v, hipStream_t st);
 
 // Power iteration support (per stage, diagonal-mix operator with scales sc):
 // given v and w = A v: z = D^-1 w; part[blk*3*ns + 3 s + {0,1,2}] =

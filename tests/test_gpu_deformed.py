@@ -110,3 +110,72 @@ def test_deformed_full_size_sampled(R):
         got = np.array([float(vc[s, z, y, x]) for (x, y, z) in nodes])
         bound = 256 * EPS_T[torch.float32] * (alpha[s] * ma + beta[s] * ka)
         assert (np.abs(got - want) <= bound).all(), (s, np.abs(got - want) / bound)
+
+
+@pytest.mark.parametrize("Q,method", [(3, "crout"), (4, "complex")])
+def test_deformed_stage_operator(R, Q, method):
+    """A context with deform != 0 applies the Krylov operator of eq. (irk:A)
+    (or the complex method's blocks) with the deformed M and K."""
+    from oracle.deformed import DeformedProblem
+    from oracle.tableau import RadauIIA
+    from oracle.complex_irk import ComplexBlocks, block_operator
+    from oracle.step import premultiplied_operator
+    from paper_2209_06700_amd.synthetic import random_vector
+    n, k, tau, eps = 3, 3, 0.03, 0.08
+    N = n * k + 1
+    p = DeformedProblem(n, k, eps)
+    m = R.RK_METHOD_COMPLEX if method == "complex" else R.RK_METHOD_CROUT
+    ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(deform=eps, method=m), eig_max=[1.0] * R.n_levels(n))
+    try:
+        u = random_vector((Q, N ** 3), seed=4, zero_boundary_N=N)
+        ud = torch.tensor(u, device="cuda")
+        vd = torch.empty_like(ud)
+        form = R.RK_OP_CBLOCKS if method == "complex" else R.RK_OP_CALA
+        R.rk_apply_operator(ctx, form, ud, vd)
+        with pytest.raises(R.RKError):
+            R.rk_apply_operator(ctx, R.RK_OP_BLOCKS, ud, vd)
+        torch.cuda.synchronize()
+        got = np.stack([p.to_int(x) for x in vd.cpu().numpy().reshape(Q, -1)])
+    finally:
+        R.rk_destroy(ctx)
+    ui = np.stack([p.to_int(x) for x in u])
+    if method == "complex":
+        want = block_operator(ComplexBlocks(RadauIIA(Q)), p.M, p.K, tau, ui)
+    else:
+        want = (premultiplied_operator(p.M, p.K, RadauIIA(Q).Ainv, tau) @ ui.reshape(-1)).reshape(Q, -1)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("n,k,Q,eps,method,prec", [
+    (4, 2, 2, 0.05, "crout", "fp64"),
+    (3, 3, 3, 0.1, "crout", "mixed"),
+    (4, 2, 4, 0.08, "complex", "mixed"),
+    (6, 2, 3, -0.05, "crout", "fp64"),
+])
+def test_deformed_step_vs_direct(R, n, k, Q, eps, method, prec):
+    """A Radau IIA step on the deformed mesh (affine-mesh V-cycles as the
+    preconditioner) against the oracle's direct solve of the deformed stage
+    system, with a source term."""
+    from oracle.deformed import DeformedProblem
+    from oracle.step import DirectStepper
+    from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import random_vector
+    print(f"deformed step n={n} k={k} Q={Q} eps={eps} {method} {prec}", flush=True)
+    tau = 0.02
+    N = n * k + 1
+    p = DeformedProblem(n, k, eps)
+    tab = RadauIIA(Q)
+    y0 = random_vector(N ** 3, seed=6, zero_boundary_N=N)
+    G = random_vector(N ** 3, seed=7, zero_boundary_N=N)
+    gam = [0.5 + 0.1 * i for i in range(Q)]
+    solver = R.RadauIIA(n, k, Q, tau, deform=eps, rtol=1e-12,
+                        method=R.RK_METHOD_COMPLEX if method == "complex" else R.RK_METHOD_CROUT,
+                        precision=R.RK_PREC_MIXED if prec == "mixed" else R.RK_PREC_FP64)
+    y = torch.tensor(y0, device="cuda")
+    stats = solver.step(0.0, y, torch.tensor(G, device="cuda"), gam)
+    solver.close()
+    want, _ = DirectStepper(p.M, p.K, tab, tau).step(p.to_int(y0), np.array(gam)[:, None] * p.to_int(G)[None, :])
+    got = p.to_int(y.cpu().numpy())
+    assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
+    assert not y.cpu().numpy()[~p.mesh.interior_mask()].any()
+    assert 0 < stats["iterations"] <= 60
