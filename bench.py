@@ -77,9 +77,10 @@ def kernel_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(cz):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+    was taken on the current kernel source with the z-chunk length `cz` that
+    the timed launches use."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -87,7 +88,7 @@ def measured_traffic():
         return None
     if rec.get("kernel_source_sha256_16") != kernel_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("by_cz", {}).get(str(cz), {}).get("hbm_bytes_per_launch")
 
 
 def _counter_rows(path, counter):
@@ -101,36 +102,50 @@ def _counter_rows(path, counter):
     return out
 
 
-def traffic_record(fetch_csv, write_csv, n=64, k=4, Q=4):
-    """HBM bytes per launch of the operator kernel: FETCH_SIZE and WRITE_SIZE
-    (KiB per dispatch, one rocprofv3 --pmc run each), each scaled by the ratio
-    of the known size of a plain device copy to what the same counter read for
-    that copy in the same run."""
+def traffic_record(fetch_csv, write_csv, cz, n=64, k=4, Q=4, reps=3):
+    """HBM bytes per launch of the operator kernel with z-chunk length cz:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch, one rocprofv3 --pmc run each,
+    RK_OP_CZ=cz for every launch of the run), averaged over the last `reps`
+    (timed) operator dispatches, each scaled by the ratio of the known size of
+    a plain device copy to what the same counter read for that copy in the
+    same run.  Merged into the record of other chunk lengths."""
     N = n * k + 1
     copy_bytes = 4.0 * Q * N ** 3
-    rec = {"kernel": OP_KERNEL, "workload": f"{n}^3 cells Q_{k}, Q={Q}, fp32 block operator",
-           "kernel_source_sha256_16": kernel_hash(), "copy_kernel": COPY_KERNEL, "copy_bytes": copy_bytes,
-           "algorithmic_bytes_per_launch": 8.0 * Q * N ** 3,
-           "commands": [f"rocprofv3 --pmc {c} -d gpurun_out/pmc_{c.split('_')[0].lower()} -o op "
-                        f"--output-format csv -- python bench.py --mode op --op-reps 3"
-                        for c in ("FETCH_SIZE", "WRITE_SIZE")]
-                       + ["python bench.py --traffic-from gpurun_out/pmc_fetch/op_counter_collection.csv "
-                          "gpurun_out/pmc_write/op_counter_collection.csv"]}
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        if rec.get("kernel_source_sha256_16") != kernel_hash() or "by_cz" not in rec:
+            rec = {}
+    except (OSError, ValueError):
+        rec = {}
+    rec.update({"kernel": OP_KERNEL, "workload": f"{n}^3 cells Q_{k}, Q={Q}, fp32 block operator",
+                "kernel_source_sha256_16": kernel_hash(), "copy_kernel": COPY_KERNEL, "copy_bytes": copy_bytes,
+                "algorithmic_bytes_per_launch": 8.0 * Q * N ** 3,
+                "commands (per chunk length CZ)": [
+                    f"RK_OP_CZ=CZ rocprofv3 --pmc {c} -d gpurun_out/pmc_{c.split('_')[0].lower()}_czCZ -o op "
+                    f"--output-format csv -- python bench.py --mode op --op-reps {reps}"
+                    for c in ("FETCH_SIZE", "WRITE_SIZE")]
+                + ["python bench.py --traffic-from gpurun_out/pmc_fetch_czCZ/op_counter_collection.csv "
+                   "gpurun_out/pmc_write_czCZ/op_counter_collection.csv --cz CZ"]})
+    rec.pop("commands", None)
+    entry = {}
     total = 0.0
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _counter_rows(path, counter)
         op = [v for nm, v in rows if nm.startswith(OP_KERNEL_MANGLED) or "op_kernel<4, float, 0, 0>" in nm]
         cp = [v for nm, v in rows if COPY_KERNEL in nm]
-        if not op or not cp:
+        if len(op) < reps or not cp:
             raise SystemExit(f"{path}: no {counter} rows for the operator or the copy kernel")
+        op = op[-reps:]
         kib_op = sum(op) / len(op)
         kib_cp = cp[-1]
         scale = copy_bytes / (kib_cp * 1024.0)
-        rec[counter] = {"op_kib_per_dispatch": kib_op, "op_dispatches": len(op), "copy_kib": kib_cp,
-                        "scale": scale, "op_bytes_per_launch": kib_op * 1024.0 * scale}
+        entry[counter] = {"op_kib_per_dispatch": kib_op, "op_dispatches": len(op), "copy_kib": kib_cp,
+                          "scale": scale, "op_bytes_per_launch": kib_op * 1024.0 * scale}
         total += kib_op * 1024.0 * scale
-    rec["hbm_bytes_per_launch"] = total
-    rec["bytes_per_stage_dof"] = total / (Q * N ** 3)
+    entry["hbm_bytes_per_launch"] = total
+    entry["bytes_per_stage_dof"] = total / (Q * N ** 3)
+    rec.setdefault("by_cz", {})[str(cz)] = entry
     return rec
 
 
@@ -239,7 +254,7 @@ def cpu_baseline_leg(torch, R, n=16, k=4, Q=4, tau=5e-4, budget_s=12.0):
 BATCH_CELLS = (4, 6, 8, 12, 16, 24, 32, 48)
 
 
-def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20):
+def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20, autotune=1):
     """The uneven batch: `count` independent heat problems, one Radau IIA step
     each, drawn with numpy.random.default_rng(seed): n^3 cells with n from
     4..48 (values with a multigrid hierarchy: n = 2^j or 3 * 2^j), degree
@@ -258,7 +273,7 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20):
         probs.append((n, k, Q, tau))
     sts = [torch.cuda.Stream() for _ in range(streams)]
     ctxs = [R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, rtol=1e-10, restart=restart,
-                       stream=sts[i % streams]) for i, (n, k, Q, tau) in enumerate(probs)]
+                       autotune=autotune, stream=sts[i % streams]) for i, (n, k, Q, tau) in enumerate(probs)]
     y0 = [torch.tensor(fourier_field(grid_coords(c.info["nodes"], n), seed=i), device="cuda")
           for i, (c, (n, _, _, _)) in enumerate(zip(ctxs, probs))]
     handles = [c.ctx for c in ctxs]
@@ -284,7 +299,8 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20):
     return {"problems": count, "recipe": f"default_rng({seed}): n in {list(BATCH_CELLS)}, k U{{1..6}}, "
                                          f"Q U{{1..5}}, tau log-uniform [1e-4, 1e-1], mixed, rtol 1e-10, "
                                          f"restart {restart}",
-            "stage_dofs": sdofs, "streams": streams, "s_concurrent": t_conc, "s_sequential": t_seq,
+            "stage_dofs": sdofs, "streams": streams, "autotune": autotune, "s_concurrent": t_conc,
+            "s_sequential": t_seq,
             "speedup": t_seq / t_conc, "stage_dof_steps_per_s": sdofs / t_conc,
             "fgmres_iterations": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
 
@@ -356,11 +372,14 @@ def main():
     ap.add_argument("--cheb-range", type=float, default=None, help="Chebyshev range (library default if unset)")
     ap.add_argument("--mode", choices=["full", "op"], default="full",
                     help="op: only the batched fp32 block operator launches (for counter runs)")
+    ap.add_argument("--cz", type=int, default=None, help="z-chunk length of the counter runs (--traffic-from)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic record from two rocprofv3 --pmc runs of --mode op")
     args = ap.parse_args()
     if args.traffic_from:
-        rec = traffic_record(*args.traffic_from, n=args.n)
+        if args.cz is None:
+            raise SystemExit("--traffic-from needs --cz (the RK_OP_CZ of the counter runs)")
+        rec = traffic_record(*args.traffic_from, cz=args.cz, n=args.n)
         with open(TRAFFIC_FILE, "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))
@@ -389,6 +408,7 @@ def main():
             v32.copy_(u32)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "op", "kernel": OP_KERNEL, "blocks_fp32_us": t_blk * 1e6,
+                          "level_cz": solver.info["level_cz"][0], "RK_OP_CZ": os.environ.get("RK_OP_CZ"),
                           "reps": args.op_reps, "GBps": 8.0 * Q * N ** 3 / t_blk / 1e9,
                           "copy_bytes": u32.numel() * 4}), flush=True)
         return 0
@@ -412,6 +432,8 @@ def main():
     del u64, v64
     torch.cuda.empty_cache()
     sdofs = Q * N ** 3
+    # z-chunk of the timed block-operator launches (tuned at create, or forced)
+    cz0 = int(os.environ.get("RK_OP_CZ") or solver.info["level_cz"][0])
     x1 = grid_coords(solver.info["nodes"], n)
     y0 = torch.tensor(fourier_field(x1, seed=0), device="cuda")
     opts = solver.opts
@@ -523,7 +545,8 @@ def main():
             "cala_fp64_GBps": 16.0 * sdofs / t_cala / 1e9,
         },
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(cz0),
+                     "z_chunk": cz0,
                      "kernel": OP_KERNEL + " (batched block operator, all Q stages per launch)",
                      "flop_per_stage_dof": flop, "algorithmic_flop_per_launch": flop * sdofs,
                      "avg_launch_us": t_blk * 1e6,

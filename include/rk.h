@@ -131,6 +131,10 @@ typedef struct {
                                    and K y_n live on the deformed mesh with this eps
                                    (|eps| <= RK_MAX_DEFORM, see rk_deformed_apply);
                                    the preconditioner keeps the affine-mesh V-cycles */
+    int32_t autotune;           /* 1: at create, time the operator kernel's z-chunk
+                                   length (1, 2, 4, 8, 16 elements) on every level and
+                                   for the fp64 Krylov operator, and keep the fastest;
+                                   0: a size heuristic                               */
 } rk_options;
 
 typedef struct {
@@ -161,12 +165,15 @@ typedef struct {
     int32_t n_blocks, n_pairs;            /* ceil(Q/2), floor(Q/2)                  */
     double  clam_re[RK_MAX_Q], clam_im[RK_MAX_Q];   /* lam of block j (Im >= 0)     */
     double  T[RK_MAX_Q * RK_MAX_Q], U[RK_MAX_Q * RK_MAX_Q];   /* row-major, T = U^-1 */
+    int32_t level_cz[RK_MAX_LEVELS];      /* z-chunk of the level's block operator
+                                             (0: size heuristic), autotune = 1   */
+    int32_t krylov_cz;                    /* same for the fp64 Krylov operator     */
 } rk_info_t;
 
 /* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
    max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
    cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0,
-   RK_METHOD_CROUT, deform 0. */
+   RK_METHOD_CROUT, deform 0, autotune 1. */
 void rk_default_options(rk_options* opt);
 
 /* Bytes of device workspace needed for the given mesh, degree (1..6),

@@ -39,7 +39,7 @@ class rk_options(C.Structure):
                 ("coarse_cheb_degree", C.c_int32), ("cheb_range", C.c_double),
                 ("eig_safety", C.c_double), ("eig_iterations", C.c_int32),
                 ("eig_max", C.POINTER(C.c_double)), ("timing", C.c_int32), ("method", C.c_int32),
-                ("deform", C.c_double)]
+                ("deform", C.c_double), ("autotune", C.c_int32)]
 
 
 class rk_stats(C.Structure):
@@ -59,7 +59,8 @@ class rk_info_t(C.Structure):
                 ("eig_max", C.c_double * RK_MAX_LEVELS), ("nodes", C.c_double * (RK_MAX_DEGREE + 1)),
                 ("n_blocks", C.c_int32), ("n_pairs", C.c_int32),
                 ("clam_re", C.c_double * RK_MAX_Q), ("clam_im", C.c_double * RK_MAX_Q),
-                ("T", C.c_double * 81), ("U", C.c_double * 81)]
+                ("T", C.c_double * 81), ("U", C.c_double * 81),
+                ("level_cz", C.c_int32 * RK_MAX_LEVELS), ("krylov_cz", C.c_int32)]
 
 
 def load():

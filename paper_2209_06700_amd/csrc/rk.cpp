@@ -69,6 +69,7 @@ struct Level {
     void* y = nullptr;
     Coeffs blk;             // block operators lam_i M + tau K on this level
     double eig_max = 1.0;
+    int cz = 0;             // tuned z-chunk of the diagonal-mix operator (0: heuristic)
 };
 
 struct Event {
@@ -121,6 +122,7 @@ struct rk_ctx {
     std::vector<Level> lv;
     Coeffs form[F_NFORMS];         // fine-level operator coefficients
     Coeffs presb_m;                // PRESB coupling: Im(lam_j) M on slots nb + j
+    int cz_pair = 0;               // tuned z-chunk of the fine-level fp64 pair operator
     void* tmp = nullptr;           // restriction intermediate
     long long ld = 0;              // stride of the Krylov vectors (Q N3 padded to 256 bytes)
     double* V = nullptr;           // (restart+1) x ld
@@ -173,6 +175,7 @@ bool valid_options(const rk_options& o, std::string& msg) {
     }
     if (!(o.cheb_range > 1.0) || !(o.eig_safety > 0.0) || o.eig_iterations < 1) { msg = "bad Chebyshev interval settings"; return false; }
     if (o.method != RK_METHOD_CROUT && o.method != RK_METHOD_COMPLEX) { msg = "bad method"; return false; }
+    if (o.autotune != 0 && o.autotune != 1) { msg = "bad autotune flag"; return false; }
     if (!(std::fabs(o.deform) <= RK_MAX_DEFORM)) { msg = "|deform| must be <= RK_MAX_DEFORM"; return false; }
     return true;
 }
@@ -329,6 +332,14 @@ int op(rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, vo
     L.stride = N * N * N;
     L.n = n; L.s0 = s0; L.nstage = ns; L.ca = ca; L.cb = cb;
     L.stream = c->stream;
+    // tuned z-chunk: pair operators of the fine level in fp64, diagonal-mix
+    // operators of every level in the preconditioner precision
+    if (cf.pair) {
+        if (n == c->n && dtype == RK_FP64) L.cz = c->cz_pair;
+    } else if (dtype == c->pc) {
+        for (const auto& lv : c->lv)
+            if (lv.n == n) L.cz = lv.cz;
+    }
     HIPCHK(c, launch_op(L));
     return RK_OK;
 }
@@ -578,6 +589,72 @@ int estimate_eigs(rk_ctx* c) {
     return RK_OK;
 }
 
+// Average time of `reps` launches of fn() on the context stream (HIP events).
+template <typename F>
+int time_launches(rk_ctx* c, int reps, F&& fn, float* ms) {
+    hipEvent_t a, b;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    int rc = fn();                                   // warm-up
+    if (rc == RK_OK) rc = hipEventRecord(a, c->stream) == hipSuccess ? RK_OK : RK_EHIP;
+    for (int i = 0; i < reps && rc == RK_OK; ++i) rc = fn();
+    if (rc == RK_OK) rc = hipEventRecord(b, c->stream) == hipSuccess ? RK_OK : RK_EHIP;
+    if (rc == RK_OK) rc = hipEventSynchronize(b) == hipSuccess ? RK_OK : RK_EHIP;
+    if (rc == RK_OK) rc = hipEventElapsedTime(ms, a, b) == hipSuccess ? RK_OK : RK_EHIP;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != RK_OK) return fail(c, RK_EHIP, "autotune timing failed");
+    *ms /= reps;
+    return RK_OK;
+}
+
+// The tile autotuner: per level, the z-chunk length of the diagonal-mix
+// operator in the preconditioner precision (on the level's buffers, with the
+// V-cycle's stage count), and for the fine-level fp64 pair operator of the
+// Krylov method; candidates 1, 2, 4, 8, 16 elements, each timed twice over
+// four launches (interleaved), the fastest average wins.  The operator's
+// results do not depend on the choice (the work decomposition changes, the
+// arithmetic of every output does not).
+int autotune(rk_ctx* c) {
+    static const int cand[] = {1, 2, 4, 8, 16, 1, 2, 4, 8, 16};
+    const int ns = c->opt.mode == RK_BATCHED ? c->Q : 1;
+    for (size_t l = 0; l < c->lv.size(); ++l) {
+        Level& L = c->lv[l];
+        HIPCHK(c, launch_random_fill(c->pc, L.x, L.N, c->Q, 777u + (unsigned)l, c->stream));
+        float best = 0.f;
+        int pick = 0;
+        for (int cz : cand) {
+            L.cz = cz;
+            float ms = 0.f;
+            int rc = time_launches(c, 4, [&] {
+                return op(c, c->k, c->pc, EPI_STORE, L.blk, L.x, L.y, nullptr, nullptr, L.n, 0, ns, 0, 0);
+            }, &ms);
+            if (rc) return rc;
+            if (pick == 0 || ms < best) { best = ms; pick = cz; }
+        }
+        L.cz = pick;
+    }
+    // fine-level fp64 pair operator (mass input in mbuf, stiffness input in w)
+    HIPCHK(c, launch_random_fill(RK_FP64, c->mbuf, c->N, c->Q, 4242u, c->stream));
+    HIPCHK(c, launch_random_fill(RK_FP64, c->w, c->N, c->Q, 4243u, c->stream));
+    if (!c->deformed) {
+        float best = 0.f;
+        int pick = 0;
+        for (int cz : cand) {
+            c->cz_pair = cz;
+            float ms = 0.f;
+            int rc = time_launches(c, 4, [&] {
+                return op(c, c->k, RK_FP64, EPI_STORE, c->form[F_CALA], c->mbuf, c->kv, nullptr, nullptr, c->n, 0,
+                          c->Q, 0, 0, c->w);
+            }, &ms);
+            if (rc) return rc;
+            if (pick == 0 || ms < best) { best = ms; pick = cz; }
+        }
+        c->cz_pair = pick;
+    }
+    return RK_OK;
+}
+
 // Arnoldi step j for every group (independent system) at once.  The basis is
 // stored unnormalised, V_i = sig[i][g] Vhat_i on group g, with the scale
 // factors sig on the device, so no separate normalisation pass is needed.
@@ -819,6 +896,7 @@ void rk_default_options(rk_options* o) {
     o->timing = 0;
     o->method = RK_METHOD_CROUT;
     o->deform = 0.0;
+    o->autotune = 1;
 }
 
 int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {
@@ -928,6 +1006,9 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
     } else if ((rc = estimate_eigs(c))) {
         g_create_error = c->err; delete c; return rc;
     }
+    if (c->opt.autotune && (rc = autotune(c))) {
+        g_create_error = c->err; delete c; return rc;
+    }
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { delete c; return fail(nullptr, RK_EHIP, hipGetErrorString(e)); }
     *out = c;
@@ -960,6 +1041,8 @@ int rk_info(const rk_ctx* c, rk_info_t* o) {
     o->n_pairs = c->tab.npair;
     for (int i = 0; i < Q; ++i) { o->clam_re[i] = c->tab.clam_re[i]; o->clam_im[i] = c->tab.clam_im[i]; }
     for (int i = 0; i < Q * Q; ++i) { o->T[i] = c->tab.CT[i]; o->U[i] = c->tab.CU[i]; }
+    for (size_t l = 0; l < c->lv.size(); ++l) o->level_cz[l] = c->lv[l].cz;
+    o->krylov_cz = c->cz_pair;
     return RK_OK;
 }
 

@@ -106,6 +106,7 @@ struct OpLaunch {
     // from b instead of read); EPI_CHEB1: the input is c0 D^-1 b
     int xo_from_b = 0;
     double c0 = 0.0;
+    int cz = 0;                // elements per z-chunk of a work item (0: size heuristic)
     hipStream_t stream = nullptr;
 };
 hipError_t launch_op(const OpLaunch& L);

@@ -56,8 +56,8 @@ def _check(rc: int, ctx: Context | None = None):
 def rk_default_options(**kw) -> rk_options:
     """Options struct with the library defaults, overridden by keywords
     (precision, mode, rtol, max_iter, restart, cheb_degree, coarse_cheb_degree,
-    cheb_range, eig_safety, eig_iterations, timing, method, deform; eig_max is
-    set by rk_create)."""
+    cheb_range, eig_safety, eig_iterations, timing, method, deform, autotune;
+    eig_max is set by rk_create)."""
     o = rk_options()
     LIB.rk_default_options(C.byref(o))
     for k, v in kw.items():
@@ -148,7 +148,7 @@ def rk_info(ctx: Context) -> dict:
                 eig_max=list(i.eig_max[:nl]), nodes=list(i.nodes[:i.degree + 1]),
                 n_blocks=i.n_blocks, n_pairs=i.n_pairs,
                 clam=[complex(i.clam_re[j], i.clam_im[j]) for j in range(i.n_blocks)],
-                T=mat(i.T), U=mat(i.U))
+                T=mat(i.T), U=mat(i.U), level_cz=list(i.level_cz[:nl]), krylov_cz=i.krylov_cz)
 
 
 def rk_step(ctx: Context, t_n: float, y: torch.Tensor, G: torch.Tensor | None = None,

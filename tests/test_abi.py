@@ -46,6 +46,10 @@ def test_default_options():
 def test_default_method_and_bad_method():
     from paper_2209_06700_amd import rk as R
     assert R.rk_default_options().method == R.RK_METHOD_CROUT
+    assert R.rk_default_options().autotune == 1 and R.rk_default_options().deform == 0.0
+    for kw in (dict(autotune=2), dict(deform=0.2)):
+        with pytest.raises(R.RKError):
+            R.rk_workspace_bytes(4, 2, 2, R.rk_default_options(**kw))
     with pytest.raises(R.RKError):
         R.rk_workspace_bytes(4, 2, 2, R.rk_default_options(method=7))
     assert R.rk_workspace_bytes(4, 2, 3, R.rk_default_options(method=R.RK_METHOD_COMPLEX)) > 0

@@ -161,3 +161,56 @@ def test_setup_tableau_matches_oracle(R, Q):
         # S is ill-conditioned for large Q; entries agree to ~cond(S) eps
         tol = 1e-13 if key not in ("S", "Sinv") else 1e-13 * np.linalg.cond(tab.S)
         assert np.abs(got - want).max() <= tol * scale, (key, np.abs(got - want).max())
+
+
+def test_results_do_not_depend_on_the_z_chunk(R):
+    """The operator kernel's z-chunk length (tuned per level by the
+    autotuner) changes only the work decomposition: V-cycles (every epilogue
+    and the transfers), the block operator and the pair operator give
+    bitwise equal results for chunks of 1, 2 and 16 elements."""
+    import os
+    from paper_2209_06700_amd.synthetic import random_vector
+    n, k, Q, tau = 8, 3, 3, 0.02
+    N = n * k + 1
+    b = random_vector((Q, N ** 3), seed=9, zero_boundary_N=N)
+    outs = {}
+    try:
+        for cz in ("1", "2", "16"):
+            os.environ["RK_OP_CZ"] = cz
+            for prec, dt in ((R.RK_PREC_FP64, torch.float64), (R.RK_PREC_MIXED, torch.float32)):
+                ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(precision=prec), eig_max=[2.0, 2.1, 2.2, 2.3])
+                bb = torch.tensor(b, device="cuda", dtype=dt)
+                x = torch.empty_like(bb)
+                R.rk_vcycle(ctx, bb, x)
+                v = torch.empty_like(bb)
+                R.rk_apply_operator(ctx, R.RK_OP_BLOCKS, bb, v)
+                b64 = bb.double()
+                w = torch.empty_like(b64)
+                R.rk_apply_operator(ctx, R.RK_OP_CALA, b64, w)
+                torch.cuda.synchronize()
+                outs[(cz, prec)] = (x.cpu(), v.cpu(), w.cpu())
+                R.rk_destroy(ctx)
+    finally:
+        os.environ.pop("RK_OP_CZ", None)
+    for prec in (R.RK_PREC_FP64, R.RK_PREC_MIXED):
+        for cz in ("2", "16"):
+            for a, c in zip(outs[("1", prec)], outs[(cz, prec)]):
+                assert torch.equal(a, c), (cz, prec)
+
+
+def test_autotune_picks_valid_chunks(R):
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
+    n, k, Q, tau = 16, 3, 3, 0.01
+    s = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED)            # autotune is the default
+    info = s.info
+    assert all(c in (1, 2, 4, 8, 16) for c in info["level_cz"]) and info["krylov_cz"] in (1, 2, 4, 8, 16)
+    plain = R.RadauIIA(n, k, Q, tau, autotune=0, precision=R.RK_PREC_MIXED)
+    assert not any(plain.info["level_cz"]) and plain.info["krylov_cz"] == 0
+    y0 = torch.tensor(fourier_field(grid_coords(info["nodes"], n), seed=2), device="cuda")
+    y1, y2 = y0.clone(), y0.clone()
+    st1 = s.step(0.0, y1)
+    st2 = plain.step(0.0, y2)
+    assert st1["iterations"] == st2["iterations"]
+    assert torch.equal(y1, y2)
+    s.close()
+    plain.close()
