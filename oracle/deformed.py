@@ -29,7 +29,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .assemble import Mesh, restrict_interior
+from .assemble import Mesh, prolongation_3d, restrict_interior
 from .fe import Element1D
 
 
@@ -179,3 +179,28 @@ def sampled_rows(n, k, eps, u_full, nodes, absolute=False):
         out_m.append(mv)
         out_k.append(kv)
     return np.array(out_m), np.array(out_k)
+
+
+class DeformedHierarchy:
+    """Level matrices of the deformed mesh on every multigrid level (n, n/2,
+    ... while even), each rediscretised on its own mesh mapped by the same
+    Phi, with the interior prolongations of the affine hierarchy: the coarse
+    space is nested in the fine one because a coarse cell's reference
+    polynomials are polynomials in the reference coordinates of its fine
+    cells (the fine cells are images of halves of the coarse reference cube
+    under the same map).  Duck-types oracle.multigrid.Hierarchy for BlockMG."""
+
+    def __init__(self, n: int, k: int, eps: float):
+        from .multigrid import level_sizes
+        self.k = k
+        self.sizes = level_sizes(n)
+        self.levels = [DeformedProblem(m, k, eps) for m in self.sizes]
+        self.P = []
+        for l in range(len(self.sizes) - 1):
+            fine, coarse = self.levels[l], self.levels[l + 1]
+            Pf = prolongation_3d(coarse.mesh)
+            self.P.append(Pf[fine.idx][:, coarse.idx].tocsr())
+
+    @property
+    def nlevels(self):
+        return len(self.levels)

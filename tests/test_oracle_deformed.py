@@ -95,3 +95,42 @@ def test_sampled_rows_equal_assembled_rows():
     rows = [a + N * (b + N * c) for a, b, c in nodes]
     np.testing.assert_allclose(m, (M @ u)[rows], atol=1e-15)
     np.testing.assert_allclose(kk, (K @ u)[rows], atol=1e-12)
+
+
+def test_deformed_hierarchy_nested_and_affine_limit():
+    """eps = 0 gives the affine hierarchy.  With eps != 0 the spaces stay
+    nested (the same P), and the Galerkin product P^T M_f P differs from the
+    rediscretised coarse matrix only by the quadrature error of the curved
+    cells (it would be equal with exact integration)."""
+    from oracle.deformed import DeformedHierarchy
+    from oracle.multigrid import Hierarchy
+    h0 = DeformedHierarchy(4, 2, 0.0)
+    ha = Hierarchy(4, 2, "cell")
+    for a, b in zip(h0.levels, ha.levels):
+        assert abs(a.M - b.M).max() <= 1e-15 and abs(a.K - b.K).max() <= 1e-13
+    h = DeformedHierarchy(4, 2, 0.08)
+    for l in range(h.nlevels - 1):
+        PtMP = h.P[l].T @ h.levels[l].M @ h.P[l]
+        Mc = h.levels[l + 1].M
+        # Galerkin product and rediscretisation differ only by quadrature error
+        assert abs(PtMP - Mc).max() <= 0.05 * abs(Mc).max()
+
+
+def test_vcycle_on_deformed_levels_contracts():
+    from oracle.deformed import DeformedHierarchy
+    from oracle.multigrid import BlockMG
+    from oracle.tableau import RadauIIA
+    tab = RadauIIA(2)
+    h = DeformedHierarchy(8, 2, 0.08)
+    mg = BlockMG(h, tab.lam, 0.05, degree=3)
+    A = mg.A[0][0]
+    n = A.shape[0]
+    rng = np.random.default_rng(3)
+    e = rng.standard_normal(n)
+    e0 = np.sqrt(e @ (A @ e))
+    for _ in range(3):
+        e = e - mg.vcycle_block(0, A @ e)
+    assert np.sqrt(e @ (A @ e)) < 0.2 ** 3 * e0
+    b1, b2 = rng.standard_normal(n), rng.standard_normal(n)
+    v1, v2 = mg.vcycle_block(1, b1), mg.vcycle_block(1, b2)
+    assert abs(v1 @ b2 - b1 @ v2) < 1e-12 * abs(v1 @ b2)
