@@ -130,11 +130,15 @@ typedef struct {
     double  deform;             /* 0: the affine mesh.  Otherwise the Krylov operator
                                    and K y_n live on the deformed mesh with this eps
                                    (|eps| <= RK_MAX_DEFORM, see rk_deformed_apply);
-                                   the preconditioner keeps the affine-mesh V-cycles */
+                                   the V-cycles as selected by deform_mg             */
     int32_t autotune;           /* 1: at create, time the operator kernel's z-chunk
                                    length (1, 2, 4, 8, 16 elements) on every level and
                                    for the fp64 Krylov operator, and keep the fastest;
                                    0: a size heuristic                               */
+    int32_t deform_mg;          /* deform != 0 only.  1: V-cycles on the deformed
+                                   levels (each level rediscretised on its mapped mesh,
+                                   stored Jacobi diagonals, Chebyshev updates as
+                                   separate passes); 0: affine-mesh V-cycles          */
 } rk_options;
 
 typedef struct {
@@ -173,7 +177,7 @@ typedef struct {
 /* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
    max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
    cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0,
-   RK_METHOD_CROUT, deform 0, autotune 1. */
+   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1. */
 void rk_default_options(rk_options* opt);
 
 /* Bytes of device workspace needed for the given mesh, degree (1..6),

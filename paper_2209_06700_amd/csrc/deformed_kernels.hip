@@ -340,6 +340,137 @@ __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
     }
 }
 
+// Jacobi diagonals of the deformed-mesh M and K: per cell of one colour and
+// node (a, b, c) of the cell,
+//   diag M += sum_q m_q  B_a^2 B_b^2 B_c^2,
+//   diag K += sum_q grad(phi)^T G_q grad(phi) with grad(phi) = (D_a B_b B_c,
+//             B_a D_b B_c, B_a B_b D_c) at point q,
+// B = gB, D = gBd (values and derivatives of the GLL basis at the Gauss
+// points).  One thread per node, the cell's geometry staged in LDS.
+template <int K, typename T>
+__global__ void __launch_bounds__(512) deformed_diag_kernel(const T* __restrict__ geo, T* __restrict__ dM,
+                                                            T* __restrict__ dK, int n, int bx, int by, int bz,
+                                                            int ccx, int ccy, long long ncell) {
+    constexpr auto& E = elem::Table<K>::d;
+    constexpr int NQ = K + 1, N2 = NQ * NQ, NP = N2 * NQ;
+    constexpr int CPW = 512 / NP;
+    __shared__ T sg[CPW * kGeo * NP];
+    const int tid = threadIdx.x;
+    const int lc = tid / NP;
+    const bool lane = lc < CPW;
+    const int r = tid - lc * NP;
+    const int a = r % NQ, b = (r / NQ) % NQ, c = r / N2;
+    const long long cid = (long long)blockIdx.x * CPW + lc;
+    const bool valid = lane && cid < ncell;
+    int cx = 0, cy = 0, cz = 0;
+    if (valid) {
+        cx = 2 * (int)(cid % ccx) + bx;
+        cy = 2 * (int)((cid / ccx) % ccy) + by;
+        cz = 2 * (int)(cid / ((long long)ccx * ccy)) + bz;
+    }
+    const long long cell = (long long)cx + (long long)n * (cy + (long long)n * cz);
+    if (lane)
+        for (int i = r; i < kGeo * NP; i += NP) sg[lc * kGeo * NP + i] = valid ? geo[cell * (kGeo * NP) + i] : T(0);
+    __syncthreads();
+    if (!valid) return;
+    // squares and products of the 1D values at this node's a, b, c
+    T Ba[NQ], Da[NQ], Bb[NQ], Db[NQ], Bc[NQ], Dc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        Ba[q] = Da[q] = Bb[q] = Db[q] = Bc[q] = Dc[q] = T(0);
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            if (t == a) { Ba[q] = T(E.gB[q][t]); Da[q] = T(E.gBd[q][t]); }
+            if (t == b) { Bb[q] = T(E.gB[q][t]); Db[q] = T(E.gBd[q][t]); }
+            if (t == c) { Bc[q] = T(E.gB[q][t]); Dc[q] = T(E.gBd[q][t]); }
+        }
+    }
+    const T* g = sg + lc * kGeo * NP;
+    T dm = T(0), dk = T(0);
+#pragma unroll
+    for (int qz = 0; qz < NQ; ++qz)
+#pragma unroll
+        for (int qy = 0; qy < NQ; ++qy)
+#pragma unroll
+            for (int qx = 0; qx < NQ; ++qx) {
+                const int q = qx + NQ * (qy + NQ * qz);
+                const T v = Ba[qx] * Bb[qy] * Bc[qz];
+                const T gx = Da[qx] * Bb[qy] * Bc[qz], gy = Ba[qx] * Db[qy] * Bc[qz], gz = Ba[qx] * Bb[qy] * Dc[qz];
+                dm = fma(g[q] * v, v, dm);
+                const T fx = g[1 * NP + q] * gx + g[4 * NP + q] * gy + g[5 * NP + q] * gz;
+                const T fy = g[4 * NP + q] * gx + g[2 * NP + q] * gy + g[6 * NP + q] * gz;
+                const T fz = g[5 * NP + q] * gx + g[6 * NP + q] * gy + g[3 * NP + q] * gz;
+                dk = fma(fx, gx, fma(fy, gy, fma(fz, gz, dk)));
+            }
+    const int N = n * K + 1;
+    const int ix = cx * K + a, iy = cy * K + b, iz = cz * K + c;
+    if (ix > 0 && ix < N - 1 && iy > 0 && iy < N - 1 && iz > 0 && iz < N - 1) {
+        const long long node = (long long)ix + (long long)N * (iy + (long long)N * iz);
+        dM[node] += dm;
+        dK[node] += dk;
+    }
+}
+
+template <int K, typename T>
+hipError_t diag_typed(int n, const void* geo, void* dM, void* dK, hipStream_t st) {
+    constexpr int NP = (K + 1) * (K + 1) * (K + 1), CPW = 512 / NP;
+    const long long N = (long long)n * K + 1;
+    const int dt = sizeof(T) == 8 ? RK_FP64 : RK_FP32;
+    hipError_t e = launch_fill(dt, dM, N * N * N, 0.0, st);
+    if (e == hipSuccess) e = launch_fill(dt, dK, N * N * N, 0.0, st);
+    for (int colour = 0; colour < 8 && e == hipSuccess; ++colour) {
+        const int bx = colour & 1, by = (colour >> 1) & 1, bz = (colour >> 2) & 1;
+        const int ccx = (n - bx + 1) / 2, ccy = (n - by + 1) / 2, ccz = (n - bz + 1) / 2;
+        const long long ncell = (long long)ccx * ccy * ccz;
+        if (ncell == 0) continue;
+        deformed_diag_kernel<K, T><<<dim3((unsigned)((ncell + CPW - 1) / CPW)), dim3(512), 0, st>>>(
+            static_cast<const T*>(geo), static_cast<T*>(dM), static_cast<T*>(dK), n, bx, by, bz, ccx, ccy, ncell);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// Streaming Chebyshev pieces with stored diagonals: D_s = alpha_s dM + beta_s dK.
+struct VecScal {
+    double alpha[RK_MAX_Q], beta[RK_MAX_Q];
+};
+
+// x_new = x + ca (x - xo) + cb D^-1 (b - t) on interior nodes (xo null: 0;
+// x null: 0), 0 on boundary nodes; x_new may alias x or xo.  Stages
+// [0, nstage) of vectors with stage stride N^3.
+template <typename T>
+__global__ void __launch_bounds__(256) cheb_vec_kernel(T* xn, const T* x, const T* xo, const T* __restrict__ b,
+                                                       const T* __restrict__ t, const T* __restrict__ dM,
+                                                       const T* __restrict__ dK, VecScal sc, double ca, double cb,
+                                                       int N, int nstage) {
+    const long long N3 = (long long)N * N * N;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < N3 * nstage;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int s = (int)(idx / N3);
+        const long long r = idx - s * N3;
+        const int z = (int)(r / ((long long)N * N));
+        const int rr = (int)(r - (long long)z * N * N);
+        const int y = rr / N, xx = rr - y * N;
+        T out = T(0);
+        if (xx > 0 && xx < N - 1 && y > 0 && y < N - 1 && z > 0 && z < N - 1) {
+            const T D = T(sc.alpha[s]) * dM[r] + T(sc.beta[s]) * dK[r];
+            const T xv = x ? x[idx] : T(0);
+            const T xov = xo ? xo[idx] : T(0);
+            const T tv = t ? t[idx] : T(0);
+            out = xv + T(ca) * (xv - xov) + T(cb) * (b[idx] - tv) / D;
+        }
+        xn[idx] = out;
+    }
+}
+
+// v = b - v (the residual after an operator application), any type
+template <typename T>
+__global__ void __launch_bounds__(256) resid_vec_kernel(T* v, const T* __restrict__ b, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        v[i] = b[i] - v[i];
+}
+
 template <int K, typename T>
 hipError_t launch_typed(int n, int Q, const double* alpha, const double* beta, const void* geo,
                         const void* um, const void* u, void* v, hipStream_t st) {
@@ -402,6 +533,43 @@ hipError_t launch_deformed_geometry(int k, int dtype, int n, double eps, void* g
         default: return hipErrorInvalidValue;
     }
 #undef RK_DEF_GEO
+}
+
+hipError_t launch_deformed_diag(int k, int dtype, int n, const void* geo, void* dM, void* dK, hipStream_t st) {
+#define RK_DEF_DIAG(KK)                                                                    \
+    case KK:                                                                               \
+        return dtype == RK_FP64 ? diag_typed<KK, double>(n, geo, dM, dK, st)               \
+                                : diag_typed<KK, float>(n, geo, dM, dK, st);
+    switch (k) {
+        RK_DEF_DIAG(1) RK_DEF_DIAG(2) RK_DEF_DIAG(3) RK_DEF_DIAG(4) RK_DEF_DIAG(5) RK_DEF_DIAG(6)
+        default: return hipErrorInvalidValue;
+    }
+#undef RK_DEF_DIAG
+}
+
+hipError_t launch_cheb_vec(int dtype, void* xn, const void* x, const void* xo, const void* b, const void* t,
+                           const void* dM, const void* dK, const double* alpha, const double* beta, double ca,
+                           double cb, int N, int nstage, hipStream_t st) {
+    VecScal sc{};
+    for (int s = 0; s < nstage && s < RK_MAX_Q; ++s) { sc.alpha[s] = alpha[s]; sc.beta[s] = beta[s]; }
+    const long long total = (long long)N * N * N * nstage;
+    const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 1 << 16);
+    if (dtype == RK_FP64)
+        cheb_vec_kernel<double><<<blocks, 256, 0, st>>>((double*)xn, (const double*)x, (const double*)xo,
+                                                        (const double*)b, (const double*)t, (const double*)dM,
+                                                        (const double*)dK, sc, ca, cb, N, nstage);
+    else
+        cheb_vec_kernel<float><<<blocks, 256, 0, st>>>((float*)xn, (const float*)x, (const float*)xo,
+                                                       (const float*)b, (const float*)t, (const float*)dM,
+                                                       (const float*)dK, sc, ca, cb, N, nstage);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_vec(int dtype, void* v, const void* b, long long n, hipStream_t st) {
+    const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 1 << 16);
+    if (dtype == RK_FP64) resid_vec_kernel<double><<<blocks, 256, 0, st>>>((double*)v, (const double*)b, n);
+    else resid_vec_kernel<float><<<blocks, 256, 0, st>>>((float*)v, (const float*)b, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_deformed_apply(int k, int dtype, int n, int Q, const double* alpha, const double* beta,

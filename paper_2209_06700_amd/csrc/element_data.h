@@ -56,6 +56,7 @@ struct Data {
     double P[2 * K + 1][K + 1];      // cell-to-halves prolongation
     double gB[K + 1][K + 1];         // GLL basis at the Gauss points, [q][a]
     double gD[K + 1][K + 1];         // collocation derivative on the Gauss points, [q][p]
+    double gBd[K + 1][K + 1];        // GLL basis derivatives at the Gauss points, [q][a]
 };
 
 template <int K>
@@ -109,6 +110,7 @@ constexpr Data<K> make() {
             B[q][a] = v;
             D[q][a] = dv;
             d.gB[q][a] = v;
+            d.gBd[q][a] = dv;
         }
     for (int q = 0; q < n; ++q)
         for (int p = 0; p < n; ++p) {

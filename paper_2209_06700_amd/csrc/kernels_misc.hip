@@ -455,7 +455,9 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) power_partial_kernel(Scal<T> sc, int k,
                                                                const T* __restrict__ v, const T* __restrict__ w,
                                                                T* __restrict__ z, int n, int nstage,
-                                                               double* __restrict__ part) {
+                                                               double* __restrict__ part,
+                                                               const T* __restrict__ dMv,
+                                                               const T* __restrict__ dKv) {
     __shared__ double sh[kBlock / 64];
     const int nK = n * k, N = nK + 1;
     const long long N3 = (long long)N * N * N;
@@ -469,7 +471,8 @@ __global__ void __launch_bounds__(kBlock) power_partial_kernel(Scal<T> sc, int k
             const long long off = (long long)s * N3 + r;
             T zv = T(0);
             if (x > 0 && x < nK && y > 0 && y < nK && zc > 0 && zc < nK) {
-                const double D = (double)jacobi_diag(k, sc.alpha[s], sc.beta[s], x, y, zc);
+                const double D = dMv ? (double)sc.alpha[s] * (double)dMv[r] + (double)sc.beta[s] * (double)dKv[r]
+                                     : (double)jacobi_diag(k, sc.alpha[s], sc.beta[s], x, y, zc);
                 const double vv = (double)v[off], wv = (double)w[off];
                 vw = fma(vv, wv, vw);
                 vdv = fma(vv * D, vv, vdv);
@@ -678,11 +681,12 @@ hipError_t launch_copy(int dtype, const void* src, void* dst, long long n, hipSt
 }
 
 hipError_t launch_power_partial(int k, int dtype, const StageScal& sc, const void* v, const void* w, void* z,
-                                int n, int nstage, double* part, int nblocks, hipStream_t st) {
+                                int n, int nstage, double* part, int nblocks, hipStream_t st, const void* dMv,
+                                const void* dKv) {
     if (dtype == RK_FP64)
-        power_partial_kernel<double><<<nblocks, kBlock, 0, st>>>(to_scal<double>(sc), k, (const double*)v, (const double*)w, (double*)z, n, nstage, part);
+        power_partial_kernel<double><<<nblocks, kBlock, 0, st>>>(to_scal<double>(sc), k, (const double*)v, (const double*)w, (double*)z, n, nstage, part, (const double*)dMv, (const double*)dKv);
     else
-        power_partial_kernel<float><<<nblocks, kBlock, 0, st>>>(to_scal<float>(sc), k, (const float*)v, (const float*)w, (float*)z, n, nstage, part);
+        power_partial_kernel<float><<<nblocks, kBlock, 0, st>>>(to_scal<float>(sc), k, (const float*)v, (const float*)w, (float*)z, n, nstage, part, (const float*)dMv, (const float*)dKv);
     return hipGetLastError();
 }
 

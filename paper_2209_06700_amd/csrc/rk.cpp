@@ -70,6 +70,12 @@ struct Level {
     Coeffs blk;             // block operators lam_i M + tau K on this level
     double eig_max = 1.0;
     int cz = 0;             // tuned z-chunk of the diagonal-mix operator (0: heuristic)
+    // multigrid on the deformed mesh: per-point geometry, Jacobi diagonals of
+    // M and K, and an operator output temp ([Q][N3]), preconditioner dtype
+    void* geo = nullptr;
+    void* dMv = nullptr;
+    void* dKv = nullptr;
+    void* t = nullptr;
 };
 
 struct Event {
@@ -114,6 +120,7 @@ struct rk_ctx {
     int pc = RK_FP64;              // preconditioner dtype
     bool cplx = false;             // direct diagonalisation with PRESB
     bool deformed = false;         // Krylov operator and K y_n on the deformed mesh
+    bool dmg = false;              // V-cycles on the deformed levels
     void* geo = nullptr;           // its per-point geometry (fp64)
     int ng = 1;                    // independent Krylov systems (complex: the nb blocks)
     Segs seg;                      // their segments of the Krylov vectors
@@ -176,6 +183,7 @@ bool valid_options(const rk_options& o, std::string& msg) {
     if (!(o.cheb_range > 1.0) || !(o.eig_safety > 0.0) || o.eig_iterations < 1) { msg = "bad Chebyshev interval settings"; return false; }
     if (o.method != RK_METHOD_CROUT && o.method != RK_METHOD_COMPLEX) { msg = "bad method"; return false; }
     if (o.autotune != 0 && o.autotune != 1) { msg = "bad autotune flag"; return false; }
+    if (o.deform_mg != 0 && o.deform_mg != 1) { msg = "bad deform_mg flag"; return false; }
     if (!(std::fabs(o.deform) <= RK_MAX_DEFORM)) { msg = "|deform| must be <= RK_MAX_DEFORM"; return false; }
     return true;
 }
@@ -221,11 +229,16 @@ size_t carve(rk_ctx& c, char* base) {
     Carver cv{base, 0, 0};
     const int Q = c.Q, k = c.k;
     const size_t pcs = dsize(c.pc);
-    (void)k;
     for (auto& L : c.lv) {
         L.b = cv.take(pcs * Q * L.N3);
         L.x = cv.take(pcs * Q * L.N3);
         L.y = cv.take(pcs * Q * L.N3);
+        if (c.dmg) {
+            L.geo = cv.take(pcs * deformed_geometry_elems(L.n, k));
+            L.dMv = cv.take(pcs * L.N3);
+            L.dKv = cv.take(pcs * L.N3);
+            L.t = cv.take(pcs * Q * L.N3);
+        }
     }
     // restriction intermediate: x-y restricted fine planes of the finest pair
     size_t tmp = 1;
@@ -277,6 +290,7 @@ int setup_sizes(rk_ctx& c, const rk_mesh* mesh, int degree, int Q, const rk_opti
     c.pc = c.opt.precision == RK_PREC_MIXED ? RK_FP32 : RK_FP64;
     c.cplx = c.opt.method == RK_METHOD_COMPLEX;
     c.deformed = c.opt.deform != 0.0;
+    c.dmg = c.deformed && c.opt.deform_mg == 1;
     c.lv.clear();
     for (int m : level_cells(c.n)) {
         Level L;
@@ -357,6 +371,77 @@ ChebCoef cheb_coef(double up, double range) {
     return cc;
 }
 
+// Multigrid on the deformed mesh.  The level blocks alpha_s M + beta_s K with
+// the cell-size scaling of the affine coefficients taken out (the deformed
+// operator integrates with the physical geometry).
+void level_ab(const Level& L, int s0, int ns, double* al, double* be) {
+    const double h3 = L.h * L.h * L.h;
+    for (int s = 0; s < ns; ++s) {
+        al[s] = L.blk.alpha[s0 + s] / h3;
+        be[s] = L.blk.beta[s0 + s] / L.h;
+    }
+}
+
+const void* at_slot(const void* base, size_t bytes) { return base ? (const char*)base + bytes : nullptr; }
+void* at_slot(void* base, size_t bytes) { return base ? (char*)base + bytes : nullptr; }
+
+// v = (blocks of level l) u for stages [s0, s0+ns), deformed mesh.
+int dlevel_op(rk_ctx* c, int l, int s0, int ns, const void* u, void* v) {
+    Level& L = c->lv[l];
+    const size_t off = dsize(c->pc) * s0 * L.N3;
+    double al[RK_MAX_Q], be[RK_MAX_Q];
+    level_ab(L, s0, ns, al, be);
+    HIPCHK(c, launch_deformed_apply(c->k, c->pc, L.n, ns, al, be, L.geo, at_slot(u, off), at_slot(u, off),
+                                    at_slot(v, off), c->stream));
+    return RK_OK;
+}
+
+// The Chebyshev iteration on the deformed levels: the same iterates as the
+// fused affine version (x_1 = c0 D^-1 b from a zero start, the same
+// three-term coefficients), with the operator applied into the level's temp
+// and the update as a separate pass over stored diagonals.
+int chebyshev_dmg(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, void* second,
+                  double up, double range, bool zero_start, int degree, void** res) {
+    Level& L = c->lv[l];
+    const double lo = up / range, theta = 0.5 * (up + lo), delta = 0.5 * (up - lo), sigma = theta / delta;
+    const double c0 = 1.0 / theta;
+    const size_t off = dsize(c->pc) * s0 * L.N3;
+    double al[RK_MAX_Q], be[RK_MAX_Q];
+    level_ab(L, s0, ns, al, be);
+    const void* bb = at_slot(b, off);
+    void* t = at_slot(L.t, off);
+    void* cur;
+    void* prev;
+    if (zero_start) {
+        HIPCHK(c, launch_cheb_vec(c->pc, at_slot(first, off), nullptr, nullptr, bb, nullptr, L.dMv, L.dKv, al, be,
+                                  0.0, c0, L.N, ns, c->stream));
+        cur = first;
+        prev = nullptr;
+    } else {
+        int rc = dlevel_op(c, l, s0, ns, first, L.t);
+        if (rc) return rc;
+        HIPCHK(c, launch_cheb_vec(c->pc, at_slot(second, off), at_slot(first, off), nullptr, bb, t, L.dMv, L.dKv,
+                                  al, be, 0.0, c0, L.N, ns, c->stream));
+        cur = second;
+        prev = first;
+    }
+    double rho = 1.0 / sigma;
+    for (int j = 1; j < degree; ++j) {
+        const double rho_new = 1.0 / (2.0 * sigma - rho);
+        const double ca = rho_new * rho, cb = 2.0 * rho_new / delta;
+        int rc = dlevel_op(c, l, s0, ns, cur, L.t);
+        if (rc) return rc;
+        void* out = prev ? prev : (cur == first ? second : first);
+        HIPCHK(c, launch_cheb_vec(c->pc, at_slot(out, off), at_slot(cur, off), prev ? at_slot(prev, off) : nullptr,
+                                  bb, t, L.dMv, L.dKv, al, be, ca, cb, L.N, ns, c->stream));
+        prev = cur;
+        cur = out;
+        rho = rho_new;
+    }
+    *res = cur;
+    return RK_OK;
+}
+
 // Chebyshev iteration of `degree` steps on level l for stages [s0, s0+ns).
 // first/second: stage-0 base pointers of the two iterate buffers.  If
 // zero_start, x_0 = 0; otherwise x_0 is in `first`.  Returns the buffer that
@@ -364,6 +449,8 @@ ChebCoef cheb_coef(double up, double range) {
 int chebyshev(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, void* second,
               bool zero_start, int degree, void** res) {
     Level& L = c->lv[l];
+    if (c->dmg) return chebyshev_dmg(c, l, s0, ns, b, first, second, L.eig_max, c->opt.cheb_range, zero_start,
+                                     degree, res);
     const ChebCoef cc = cheb_coef(L.eig_max, c->opt.cheb_range);
     const int k = c->k, dt = c->pc;
     const double c0 = 1.0 / cc.theta;          // x_1 = c0 D^-1 b from a zero start
@@ -438,8 +525,15 @@ int vcycle_level(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, v
     if (rc) return rc;
     void* spare = (pre == first) ? second : first;
     // residual into the spare buffer
-    rc = op(c, c->k, c->pc, EPI_RESID, L.blk, pre, spare, b, nullptr, L.n, s0, ns, 0, 0);
-    if (rc) return rc;
+    if (c->dmg) {
+        rc = dlevel_op(c, l, s0, ns, pre, spare);
+        if (rc) return rc;
+        const size_t off = dsize(c->pc) * s0 * L.N3;
+        HIPCHK(c, launch_resid_vec(c->pc, at_slot(spare, off), at_slot(b, off), (long long)ns * L.N3, c->stream));
+    } else {
+        rc = op(c, c->k, c->pc, EPI_RESID, L.blk, pre, spare, b, nullptr, L.n, s0, ns, 0, 0);
+        if (rc) return rc;
+    }
     rc = restrict_to(c, l, s0, ns, spare);
     if (rc) return rc;
     Level& C = c->lv[l + 1];
@@ -488,11 +582,20 @@ int presb_blocks(rk_ctx* c) {
     const int nb = c->tab.nb, np = c->tab.npair;
     int rc = vcycle_range(c, F.b, F.x, F.y, 0, nb);
     if (rc || np == 0) return rc;
-    // input slot j feeds output slot nb + j: shift the input base by -nb slots
     const size_t es = dsize(c->pc);
-    const void* g1 = (const void*)((uintptr_t)F.x - (uintptr_t)(es * nb * F.N3));
-    rc = op(c, c->k, c->pc, EPI_RESID, c->presb_m, g1, F.y, F.b, nullptr, F.n, nb, np, 0, 0);
-    if (rc) return rc;
+    if (c->dmg) {
+        // F.y[nb + j] = Im(lam_j) M g1_j on the deformed mesh, then F.b - F.y
+        double al[RK_MAX_Q], be[RK_MAX_Q];
+        for (int j = 0; j < np; ++j) { al[j] = c->tab.clam_im[j]; be[j] = 0.0; }
+        void* fy = at_slot(F.y, es * nb * F.N3);
+        HIPCHK(c, launch_deformed_apply(c->k, c->pc, F.n, np, al, be, F.geo, F.x, F.x, fy, c->stream));
+        HIPCHK(c, launch_resid_vec(c->pc, fy, at_slot(F.b, es * nb * F.N3), (long long)np * F.N3, c->stream));
+    } else {
+        // input slot j feeds output slot nb + j: shift the input base by -nb slots
+        const void* g1 = (const void*)((uintptr_t)F.x - (uintptr_t)(es * nb * F.N3));
+        rc = op(c, c->k, c->pc, EPI_RESID, c->presb_m, g1, F.y, F.b, nullptr, F.n, nb, np, 0, 0);
+        if (rc) return rc;
+    }
     return vcycle_range(c, F.y, F.x, F.b, nb, np);
 }
 
@@ -570,10 +673,14 @@ int estimate_eigs(rk_ctx* c) {
         Level& L = c->lv[l];
         if (L.N <= 2) { L.eig_max = 1.0; continue; }
         HIPCHK(c, launch_random_fill(dt, L.x, L.N, Q, 12345u + 977u * (unsigned)l, c->stream));
+        StageScal sc = to_stage_scal(L.blk);
+        if (c->dmg) level_ab(L, 0, Q, sc.alpha, sc.beta);
         for (int it = 0; it < c->opt.eig_iterations; ++it) {
-            int rc = op(c, c->k, dt, EPI_STORE, L.blk, L.x, L.y, nullptr, nullptr, L.n, 0, Q, 0, 0);
+            int rc = c->dmg ? dlevel_op(c, (int)l, 0, Q, L.x, L.y)
+                            : op(c, c->k, dt, EPI_STORE, L.blk, L.x, L.y, nullptr, nullptr, L.n, 0, Q, 0, 0);
             if (rc) return rc;
-            HIPCHK(c, launch_power_partial(c->k, dt, to_stage_scal(L.blk), L.x, L.y, L.b, L.n, Q, c->part, kRedBlocks, c->stream));
+            HIPCHK(c, launch_power_partial(c->k, dt, sc, L.x, L.y, L.b, L.n, Q, c->part, kRedBlocks, c->stream,
+                                           c->dmg ? L.dMv : nullptr, c->dmg ? L.dKv : nullptr));
             HIPCHK(c, launch_reduce(c->part, kRedBlocks, 3 * Q, c->scal, 0, c->stream));
             if (it + 1 < c->opt.eig_iterations)
                 HIPCHK(c, launch_power_normalize(dt, L.b, L.x, c->scal, L.N, Q, c->stream));
@@ -618,7 +725,7 @@ int time_launches(rk_ctx* c, int reps, F&& fn, float* ms) {
 int autotune(rk_ctx* c) {
     static const int cand[] = {1, 2, 4, 8, 16, 1, 2, 4, 8, 16};
     const int ns = c->opt.mode == RK_BATCHED ? c->Q : 1;
-    for (size_t l = 0; l < c->lv.size(); ++l) {
+    for (size_t l = 0; l < c->lv.size() && !c->dmg; ++l) {
         Level& L = c->lv[l];
         HIPCHK(c, launch_random_fill(c->pc, L.x, L.N, c->Q, 777u + (unsigned)l, c->stream));
         float best = 0.f;
@@ -897,6 +1004,7 @@ void rk_default_options(rk_options* o) {
     o->method = RK_METHOD_CROUT;
     o->deform = 0.0;
     o->autotune = 1;
+    o->deform_mg = 1;
 }
 
 int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {
@@ -999,6 +1107,11 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
     hipError_t e = hipMemcpyAsync(c->mix, mix.data(), mix.size() * 8, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess && c->deformed)
         e = launch_deformed_geometry(c->k, RK_FP64, c->n, c->opt.deform, c->geo, c->stream);
+    for (size_t l = 0; c->dmg && l < c->lv.size() && e == hipSuccess; ++l) {
+        Level& L = c->lv[l];
+        e = launch_deformed_geometry(c->k, c->pc, L.n, c->opt.deform, L.geo, c->stream);
+        if (e == hipSuccess) e = launch_deformed_diag(c->k, c->pc, L.n, L.geo, L.dMv, L.dKv, c->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { delete c; return fail(nullptr, RK_EHIP, hipGetErrorString(e)); }
     if (!c->eig_user.empty()) {

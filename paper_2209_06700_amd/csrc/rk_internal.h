@@ -186,13 +186,26 @@ size_t deformed_geometry_elems(int n, int k);
 hipError_t launch_deformed_geometry(int k, int dtype, int n, double eps, void* geo, hipStream_t st);
 hipError_t launch_deformed_apply(int k, int dtype, int n, int Q, const double* alpha, const double* beta,
                                  const void* geo, const void* um, const void* u, void* v, hipStream_t st);
+// Jacobi diagonals of the deformed-mesh M and K into dM, dK ([N^3], dtype).
+hipError_t launch_deformed_diag(int k, int dtype, int n, const void* geo, void* dM, void* dK, hipStream_t st);
+// x_new = x + ca (x - xo) + cb D^-1 (b - t), D_s = alpha_s dM + beta_s dK, on
+// interior nodes of nstage stages (x, xo, t may be null = 0; x_new may alias
+// x or xo), boundary 0.  alpha, beta: host arrays of nstage values.
+hipError_t launch_cheb_vec(int dtype, void* xn, const void* x, const void* xo, const void* b, const void* t,
+                           const void* dM, const void* dK, const double* alpha, const double* beta, double ca,
+                           double cb, int N, int nstage, hipStream_t st);
+// v = b - v, n entries of dtype
+hipError_t launch_resid_vec(int dtype, void* v, const void* b, long long n, hipStream_t st);
 
 // Power iteration support (per stage, diagonal-mix operator with scales sc):
 // given v and w = A v: z = D^-1 w; part[blk*3*ns + 3 s + {0,1,2}] =
-// {v.w, v.Dv, z.z} restricted to stage s.  Requires nstage <= RK_MAX_Q.
+// {v.w, v.Dv, z.z} restricted to stage s.  Requires nstage <= RK_MAX_Q.  With
+// dMv, dKv (stored [N^3] diagonals) D_s = alpha_s dMv + beta_s dKv, else the
+// affine-mesh diagonal from the 1D tables.
 hipError_t launch_power_partial(int k, int dtype, const StageScal& sc, const void* v,
                                 const void* w, void* z, int n, int nstage, double* part,
-                                int nblocks, hipStream_t st);
+                                int nblocks, hipStream_t st, const void* dMv = nullptr,
+                                const void* dKv = nullptr);
 // v_s = z_s / sqrt(zz_s) with zz_s = red[3 s + 2]
 hipError_t launch_power_normalize(int dtype, const void* z, void* v, const double* red, int n,
                                   int nstage, hipStream_t st);

@@ -146,21 +146,23 @@ def test_deformed_stage_operator(R, Q, method):
     assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
 
 
-@pytest.mark.parametrize("n,k,Q,eps,method,prec", [
-    (4, 2, 2, 0.05, "crout", "fp64"),
-    (3, 3, 3, 0.1, "crout", "mixed"),
-    (4, 2, 4, 0.08, "complex", "mixed"),
-    (6, 2, 3, -0.05, "crout", "fp64"),
+@pytest.mark.parametrize("n,k,Q,eps,method,prec,dmg", [
+    (4, 2, 2, 0.05, "crout", "fp64", 1),
+    (3, 3, 3, 0.1, "crout", "mixed", 1),
+    (4, 2, 4, 0.08, "complex", "mixed", 1),
+    (6, 2, 3, -0.05, "crout", "fp64", 1),
+    (4, 2, 2, 0.05, "crout", "fp64", 0),
+    (4, 2, 4, 0.08, "complex", "mixed", 0),
 ])
-def test_deformed_step_vs_direct(R, n, k, Q, eps, method, prec):
-    """A Radau IIA step on the deformed mesh (affine-mesh V-cycles as the
-    preconditioner) against the oracle's direct solve of the deformed stage
-    system, with a source term."""
+def test_deformed_step_vs_direct(R, n, k, Q, eps, method, prec, dmg):
+    """A Radau IIA step on the deformed mesh (V-cycles on the deformed
+    levels, or the affine-mesh V-cycles with dmg = 0) against the oracle's
+    direct solve of the deformed stage system, with a source term."""
     from oracle.deformed import DeformedProblem
     from oracle.step import DirectStepper
     from oracle.tableau import RadauIIA
     from paper_2209_06700_amd.synthetic import random_vector
-    print(f"deformed step n={n} k={k} Q={Q} eps={eps} {method} {prec}", flush=True)
+    print(f"deformed step n={n} k={k} Q={Q} eps={eps} {method} {prec} dmg={dmg}", flush=True)
     tau = 0.02
     N = n * k + 1
     p = DeformedProblem(n, k, eps)
@@ -168,7 +170,7 @@ def test_deformed_step_vs_direct(R, n, k, Q, eps, method, prec):
     y0 = random_vector(N ** 3, seed=6, zero_boundary_N=N)
     G = random_vector(N ** 3, seed=7, zero_boundary_N=N)
     gam = [0.5 + 0.1 * i for i in range(Q)]
-    solver = R.RadauIIA(n, k, Q, tau, deform=eps, rtol=1e-12,
+    solver = R.RadauIIA(n, k, Q, tau, deform=eps, deform_mg=dmg, rtol=1e-12,
                         method=R.RK_METHOD_COMPLEX if method == "complex" else R.RK_METHOD_CROUT,
                         precision=R.RK_PREC_MIXED if prec == "mixed" else R.RK_PREC_FP64)
     y = torch.tensor(y0, device="cuda")
@@ -179,3 +181,101 @@ def test_deformed_step_vs_direct(R, n, k, Q, eps, method, prec):
     assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
     assert not y.cpu().numpy()[~p.mesh.interior_mask()].any()
     assert 0 < stats["iterations"] <= 60
+
+
+# (n, k, Q, tau, eps, smoother degree, coarse degree)
+DMG_CASES = [(8, 2, 2, 0.05, 0.08, 3, 3), (4, 3, 3, 0.01, 0.1, 2, 4), (6, 2, 2, 0.02, -0.06, 3, 3),
+             (2, 4, 4, 0.003, 0.1, 3, 2), (4, 4, 3, 0.01, 0.05, 1, 2), (5, 2, 1, 0.05, 0.1, 3, 3)]
+
+
+@pytest.mark.parametrize("n,k,Q,tau,eps,deg,cdeg", DMG_CASES)
+@pytest.mark.parametrize("mode", ["batched", "per_stage"])
+def test_deformed_vcycle_parity_fp64(R, n, k, Q, tau, eps, deg, cdeg, mode):
+    """V-cycles on the deformed levels against the oracle's block multigrid
+    on the deformed hierarchy, explicit Chebyshev bounds; fp64 to 1e-12."""
+    from oracle.deformed import DeformedHierarchy
+    from oracle.multigrid import BlockMG
+    from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import random_vector
+    print(f"deformed vcycle n={n} k={k} Q={Q} eps={eps} {mode}", flush=True)
+    hier = DeformedHierarchy(n, k, eps)
+    tab = RadauIIA(Q)
+    mg = BlockMG(hier, tab.lam, tau, degree=deg, coarse_degree=cdeg, cheb_range=15.0)
+    fine = hier.levels[0]
+    N = n * k + 1
+    opts = R.rk_default_options(deform=eps, cheb_degree=deg, coarse_cheb_degree=cdeg, cheb_range=15.0,
+                                mode=R.RK_BATCHED if mode == "batched" else R.RK_PER_STAGE)
+    ctx = R.rk_create(n, k, Q, tau, opts, eig_max=list(mg.eig_max))
+    try:
+        b_np = random_vector((Q, N ** 3), seed=17 + n, zero_boundary_N=N)
+        x = torch.full((Q * N ** 3,), float("nan"), dtype=torch.float64, device="cuda")
+        R.rk_vcycle(ctx, torch.tensor(b_np, device="cuda").view(-1), x)
+        torch.cuda.synchronize()
+        got = x.cpu().numpy().reshape(Q, -1)
+    finally:
+        R.rk_destroy(ctx)
+    want = np.stack([fine.to_full(v) for v in mg.vcycle(np.stack([fine.to_int(v) for v in b_np]))])
+    scale = np.abs(want).max()
+    assert np.abs(got - want).max() <= 1e-12 * scale, np.abs(got - want).max() / scale
+
+
+def test_deformed_vcycle_mixed_and_eigen_bound(R):
+    """Mixed precision V-cycle on the deformed levels within 1e-4 of the fp64
+    oracle; the GPU's own Chebyshev bound on the deformed fine level lies in
+    [0.9, 1] x 1.2 x the exact largest eigenvalue of D^-1 A."""
+    from oracle.deformed import DeformedHierarchy
+    from oracle.multigrid import BlockMG
+    from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import random_vector
+    n, k, Q, tau, eps = 8, 2, 3, 0.02, 0.08
+    hier = DeformedHierarchy(n, k, eps)
+    mg = BlockMG(hier, RadauIIA(Q).lam, tau, degree=3)
+    fine = hier.levels[0]
+    N = n * k + 1
+    ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(deform=eps, precision=R.RK_PREC_MIXED),
+                      eig_max=list(mg.eig_max))
+    try:
+        b_np = random_vector((Q, N ** 3), seed=23, zero_boundary_N=N).astype(np.float32)
+        x = torch.empty(Q * N ** 3, dtype=torch.float32, device="cuda")
+        R.rk_vcycle(ctx, torch.tensor(b_np, device="cuda").view(-1), x)
+        torch.cuda.synchronize()
+        got = x.double().cpu().numpy().reshape(Q, -1)
+    finally:
+        R.rk_destroy(ctx)
+    want = np.stack([fine.to_full(v) for v in mg.vcycle(np.stack([fine.to_int(v) for v in b_np.astype(float)]))])
+    assert np.abs(got - want).max() <= 1e-4 * np.abs(want).max()
+    solver = R.RadauIIA(n, k, Q, tau, deform=eps)
+    est = solver.info["eig_max"][0]
+    solver.close()
+    exact = mg.eig_max[0]           # 1.2 x the exact largest eigenvalue over the blocks
+    assert 0.9 * exact <= est <= 1.0000001 * exact, (est, exact)
+
+
+@pytest.mark.parametrize("Q", [2, 3])
+def test_deformed_presb_parity(R, Q):
+    """PRESB on the deformed levels (complex method) against the oracle's
+    PRESB with the deformed block multigrid, fp64."""
+    from oracle.complex_irk import ComplexBlocks, Presb
+    from oracle.deformed import DeformedHierarchy
+    from oracle.multigrid import BlockMG
+    from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import random_vector
+    n, k, tau, eps = 6, 2, 0.03, 0.07
+    dec = ComplexBlocks(RadauIIA(Q))
+    hier = DeformedHierarchy(n, k, eps)
+    mg = BlockMG(hier, dec.h_shift(), tau, degree=3)
+    fine = hier.levels[0]
+    pre = Presb(dec, fine.M, lambda s, b: mg.vcycle_block(s, b))
+    N = n * k + 1
+    ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(deform=eps, method=R.RK_METHOD_COMPLEX),
+                      eig_max=list(mg.eig_max))
+    try:
+        r_np = random_vector((Q, N ** 3), seed=29, zero_boundary_N=N)
+        z = torch.empty(Q * N ** 3, dtype=torch.float64, device="cuda")
+        R.rk_apply_preconditioner(ctx, torch.tensor(r_np, device="cuda").view(-1), z)
+        torch.cuda.synchronize()
+        got = z.cpu().numpy().reshape(Q, -1)
+    finally:
+        R.rk_destroy(ctx)
+    want = np.stack([fine.to_full(v) for v in pre.apply(np.stack([fine.to_int(v) for v in r_np]))])
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
