@@ -77,3 +77,33 @@ def test_batch_entry_failure_is_isolated(R):
         R.rk_step_batch([good.ctx, bad.ctx], [0.0, 0.0], [yg, yb], threads=2)
     good.close()
     bad.close()
+
+
+def test_batch_mixes_methods_and_meshes(R):
+    """One batch holding Crout, complex (PRESB) and deformed-mesh contexts:
+    every entry equals the same step taken alone, bitwise."""
+    specs = [dict(n=6, k=2, Q=3, tau=0.01, prec="mixed"),
+             dict(n=4, k=3, Q=4, tau=0.005, prec="fp64", method=R.RK_METHOD_COMPLEX),
+             dict(n=4, k=2, Q=2, tau=0.02, prec="mixed", deform=0.06),
+             dict(n=4, k=2, Q=3, tau=0.02, prec="fp64", deform=-0.05, deform_mg=0),
+             dict(n=6, k=2, Q=5, tau=0.002, prec="mixed", method=R.RK_METHOD_COMPLEX, deform=0.04)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+
+    def make(sp, stream=None):
+        kw = {key: v for key, v in sp.items() if key not in ("n", "k", "Q", "tau", "prec")}
+        return _make(R, sp["n"], sp["k"], sp["Q"], sp["tau"], sp["prec"], stream=stream, **kw)
+
+    ctxs = [make(sp, streams[i % 3]) for i, sp in enumerate(specs)]
+    ys = [_y0(R, s, sp["n"], i) for i, (s, sp) in enumerate(zip(ctxs, specs))]
+    y_init = [y.clone() for y in ys]
+    torch.cuda.synchronize()
+    R.rk_step_batch([s.ctx for s in ctxs], [0.0] * len(ctxs), ys, threads=3)
+    torch.cuda.synchronize()
+    for sp, s, y, y0 in zip(specs, ctxs, ys, y_init):
+        alone = make(sp)
+        ya = y0.clone()
+        alone.step(0.0, ya)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ya), sp
+        alone.close()
+        s.close()
