@@ -264,9 +264,10 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
             pb[m] = ok ? beta * mx * my : T(0);
         }
     }
-    // Issue the loads of plane z into registers (zeros outside the interior).
-    // Every slot loads from a valid address (offset 0 for slots outside the
-    // interior) and selects zero afterwards.
+    // Issue the loads of plane z into registers.  Every slot loads from a
+    // valid address (offset 0 for slots outside the interior); the zeros of
+    // those slots are selected when the plane is committed to LDS, one
+    // iteration later, so that no instruction here waits for the loads.
     auto issue = [&](int z) __attribute__((always_inline)) {
         if constexpr (INB) {
             izm = diag_rt<K, 0, T>(z % K);
@@ -275,17 +276,11 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
         if (z > 0 && z < nK) {
             const char* __restrict__ pl = reinterpret_cast<const char*>(us + z * NN);
 #pragma unroll
-            for (int m = 0; m < NSLOT; ++m) {
-                const T vv = *reinterpret_cast<const T*>(pl + soff[m]);
-                pre[0][m] = (smask >> m & 1u) ? vv : T(0);
-            }
+            for (int m = 0; m < NSLOT; ++m) pre[0][m] = *reinterpret_cast<const T*>(pl + soff[m]);
             if (MIX == MIX_PAIR) {
                 const char* __restrict__ pl2 = reinterpret_cast<const char*>(us2 + z * NN);
 #pragma unroll
-                for (int m = 0; m < NSLOT; ++m) {
-                    const T vv = *reinterpret_cast<const T*>(pl2 + soff[m]);
-                    pre[NU - 1][m] = (smask >> m & 1u) ? vv : T(0);
-                }
+                for (int m = 0; m < NSLOT; ++m) pre[NU - 1][m] = *reinterpret_cast<const T*>(pl2 + soff[m]);
             }
         } else {
 #pragma unroll
@@ -300,9 +295,10 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
         for (int m = 0; m < NSLOT; ++m) {
             const int i = tid + m * NT;
             if (m < NSLOT - 1 || i < RY * RX) {
-                if constexpr (INB) dst[i] = pre[0][m] * (p.c0 * recip(fma(pa[m], izm, pb[m] * izk)));
-                else dst[i] = pre[0][m];
-                if (MIX == MIX_PAIR) dst[RY * RX + i] = pre[NU - 1][m];
+                const bool ok = smask >> m & 1u;
+                if constexpr (INB) dst[i] = ok ? pre[0][m] * (p.c0 * recip(fma(pa[m], izm, pb[m] * izk))) : T(0);
+                else dst[i] = ok ? pre[0][m] : T(0);
+                if (MIX == MIX_PAIR) dst[RY * RX + i] = ok ? pre[NU - 1][m] : T(0);
             }
         }
     };
