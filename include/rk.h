@@ -139,6 +139,13 @@ typedef struct {
                                    levels (each level rediscretised on its mapped mesh,
                                    stored Jacobi diagonals, Chebyshev updates as
                                    separate passes); 0: affine-mesh V-cycles          */
+    int32_t vc_streams;         /* batched mode: the stage blocks of a V-cycle are
+                                   split into this many groups (1..RK_MAX_Q, capped at
+                                   the block count), each group on its own stream
+                                   (forked from and joined back into the context's
+                                   stream), so that the latency-bound coarse levels
+                                   of one group overlap the fine levels of another.
+                                   Results do not depend on it.                      */
 } rk_options;
 
 typedef struct {
@@ -177,7 +184,7 @@ typedef struct {
 /* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
    max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
    cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0,
-   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1. */
+   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1, vc_streams 2. */
 void rk_default_options(rk_options* opt);
 
 /* Bytes of device workspace needed for the given mesh, degree (1..6),

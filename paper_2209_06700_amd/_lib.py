@@ -39,7 +39,8 @@ class rk_options(C.Structure):
                 ("coarse_cheb_degree", C.c_int32), ("cheb_range", C.c_double),
                 ("eig_safety", C.c_double), ("eig_iterations", C.c_int32),
                 ("eig_max", C.POINTER(C.c_double)), ("timing", C.c_int32), ("method", C.c_int32),
-                ("deform", C.c_double), ("autotune", C.c_int32), ("deform_mg", C.c_int32)]
+                ("deform", C.c_double), ("autotune", C.c_int32), ("deform_mg", C.c_int32),
+                ("vc_streams", C.c_int32)]
 
 
 class rk_stats(C.Structure):

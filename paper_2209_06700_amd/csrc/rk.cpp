@@ -117,6 +117,12 @@ struct rk_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t vc_exec = nullptr;
     int vc_graph = 0;              // 0 not tried, 1 captured, -1 eager only
+    // Split V-cycles (opt.vc_streams groups of stage blocks): group g > 0
+    // runs on aux_stream[g], forked from and joined back into `stream` by
+    // events, so that the latency-bound coarse levels of one group overlap the
+    // fine levels of another.  Created on first use.
+    hipStream_t aux_stream[RK_MAX_Q] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[RK_MAX_Q] = {};
     int pc = RK_FP64;              // preconditioner dtype
     bool cplx = false;             // direct diagonalisation with PRESB
     bool deformed = false;         // Krylov operator and K y_n on the deformed mesh
@@ -184,6 +190,7 @@ bool valid_options(const rk_options& o, std::string& msg) {
     if (o.method != RK_METHOD_CROUT && o.method != RK_METHOD_COMPLEX) { msg = "bad method"; return false; }
     if (o.autotune != 0 && o.autotune != 1) { msg = "bad autotune flag"; return false; }
     if (o.deform_mg != 0 && o.deform_mg != 1) { msg = "bad deform_mg flag"; return false; }
+    if (o.vc_streams < 1 || o.vc_streams > RK_MAX_Q) { msg = "vc_streams out of range"; return false; }
     if (!(std::fabs(o.deform) <= RK_MAX_DEFORM)) { msg = "|deform| must be <= RK_MAX_DEFORM"; return false; }
     return true;
 }
@@ -499,8 +506,10 @@ int restrict_to(rk_ctx* c, int l, int s0, int ns, const void* fine) {
     Level& F = c->lv[l];
     Level& C = c->lv[l + 1];
     const size_t es = dsize(c->pc);
+    // the intermediate holds N_f N_c^2 values per stage; stages at their own offsets
+    void* tmp = (char*)c->tmp + es * s0 * ((size_t)F.N * C.N * C.N);
     HIPCHK(c, launch_restrict(c->k, c->pc, (const char*)fine + es * s0 * F.N3, (char*)C.b + es * s0 * C.N3,
-                              c->tmp, C.n, ns, F.N3, C.N3, c->stream));
+                              tmp, C.n, ns, F.N3, C.N3, c->stream));
     return RK_OK;
 }
 
@@ -557,6 +566,36 @@ int vcycle_range(rk_ctx* c, const void* b, void* x, void* scratch, int s0, int n
     const bool res_first = single && (c->opt.coarse_cheb_degree % 2 == 1);
     void* first = res_first ? x : scratch;
     void* second = res_first ? scratch : x;
+    const int ng = std::min(c->opt.vc_streams, ns);
+    if (ng >= 2 && c->opt.mode == RK_BATCHED) {
+        if (!c->ev_fork) HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+        hipStream_t main = c->stream;
+        int rc = RK_OK;
+        for (int g = 0, sg = s0; g < ng && rc == RK_OK; ++g) {
+            const int cnt = ns / ng + (g < ns % ng ? 1 : 0);
+            if (g > 0) {
+                if (!c->aux_stream[g]) {
+                    HIPCHK(c, hipStreamCreateWithFlags(&c->aux_stream[g], hipStreamNonBlocking));
+                    HIPCHK(c, hipEventCreateWithFlags(&c->ev_join[g], hipEventDisableTiming));
+                }
+                HIPCHK(c, hipStreamWaitEvent(c->aux_stream[g], c->ev_fork, 0));
+                c->stream = c->aux_stream[g];
+            }
+            void* res = nullptr;
+            rc = vcycle_level(c, 0, sg, cnt, b, first, second, &res);
+            if (rc == RK_OK && res != x) rc = fail(c, RK_EHIP, "internal: V-cycle result buffer");
+            if (g > 0) {
+                c->stream = main;
+                if (rc == RK_OK) {
+                    HIPCHK(c, hipEventRecord(c->ev_join[g], c->aux_stream[g]));
+                    HIPCHK(c, hipStreamWaitEvent(main, c->ev_join[g], 0));
+                }
+            }
+            sg += cnt;
+        }
+        return rc;
+    }
     const int groups = c->opt.mode == RK_BATCHED ? 1 : ns;
     const int per = c->opt.mode == RK_BATCHED ? ns : 1;
     for (int g = 0; g < groups; ++g) {
@@ -1005,6 +1044,7 @@ void rk_default_options(rk_options* o) {
     o->deform = 0.0;
     o->autotune = 1;
     o->deform_mg = 1;
+    o->vc_streams = 2;
 }
 
 int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {
@@ -1133,6 +1173,11 @@ int rk_destroy(rk_ctx* c) {
     for (auto& e : c->event_pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     if (c->vc_exec) (void)hipGraphExecDestroy(c->vc_exec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (int g = 0; g < RK_MAX_Q; ++g) {
+        if (c->aux_stream[g]) (void)hipStreamDestroy(c->aux_stream[g]);
+        if (c->ev_join[g]) (void)hipEventDestroy(c->ev_join[g]);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     delete c;
     return RK_OK;
 }

@@ -57,7 +57,7 @@ def rk_default_options(**kw) -> rk_options:
     """Options struct with the library defaults, overridden by keywords
     (precision, mode, rtol, max_iter, restart, cheb_degree, coarse_cheb_degree,
     cheb_range, eig_safety, eig_iterations, timing, method, deform, autotune,
-    deform_mg; eig_max is set by rk_create)."""
+    deform_mg, vc_streams; eig_max is set by rk_create)."""
     o = rk_options()
     LIB.rk_default_options(C.byref(o))
     for k, v in kw.items():
