@@ -45,8 +45,11 @@
  *   bytes and passes it to rk_create(); the library never allocates device
  *   memory itself.  The workspace must stay alive until rk_destroy().
  *
- * Streams: all device work of a context is enqueued on the HIP stream given
- *   to rk_create() (NULL = the default stream).  rk_apply_operator(),
+ * Streams: all device work of a context is ordered on the HIP stream given
+ *   to rk_create() (NULL = the default stream).  A batched V-cycle forks the
+ *   V-cycles of some blocks onto private streams of the context (see
+ *   rk_options.vc_streams) after the work already on that stream, and joins
+ *   them back before any later work on it.  rk_apply_operator(),
  *   rk_vcycle() and rk_apply_preconditioner() are asynchronous; rk_create()
  *   and rk_step() return after their device work has finished.
  *
