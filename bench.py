@@ -26,9 +26,10 @@ Reported:
   cpu_baseline, the oracle's assembled block operator (scipy CSR SpMV) on a
   bounded sample (16^3 cells, Q_4, same Q and tau), in the same unit; and
   accuracy_vs_oracle, the error of one GPU step on the 32^3 Q_4 grid against
-  the oracle's exact step for FGMRES tolerances 1e-6 .. 1e-10.  The loosest
-  tolerance within 1e-8 then sets at_1e-8_accuracy: s per step of both forms
-  at that accuracy.
+  the oracle's exact step for FGMRES tolerances 1e-6 .. 1e-10, and
+  accuracy_vs_oracle_64cubed, the same on the 64^3 Q_4 grid of the workload.
+  The loosest tolerance within 1e-8 on both grids then sets at_1e-8_accuracy:
+  s per step of each form at that accuracy.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        python bench.py --mode op [--op-reps R]      (operator launches + one
@@ -201,8 +202,9 @@ def cpu_baseline_leg(torch, R, n=16, k=4, Q=4, tau=5e-4, budget_s=12.0):
     """The host-side leg, the only part of the bench that runs the oracle:
     * the oracle's assembled block operator v_i = (lam_i M + tau K) u_i by CSR
       SpMV (scipy, one thread) on a bounded sample, timed on the host cores;
-    * the oracle's exact (modal) Radau IIA step on the 32^3 Q_4 grid, the
-      reference for the error of GPU steps at several FGMRES tolerances."""
+    * the oracle's exact (modal) Radau IIA step on the 32^3 Q_4 grid and on
+      the 64^3 Q_4 grid of the workload itself, the references for the error
+      of GPU steps at several FGMRES tolerances."""
     import numpy as np
     from oracle.assemble import Problem
     from oracle.step import ModalSolver
@@ -224,18 +226,28 @@ def cpu_baseline_leg(torch, R, n=16, k=4, Q=4, tau=5e-4, budget_s=12.0):
            "sample": f"assembled block operator (lam_i M + tau K, scipy CSR SpMV, single thread) on "
                      f"{n}^3 cells Q_{k} (N={N}), Q={Q}, {reps} applies in {t:.1f} s",
            "host_cpu_count": os.cpu_count()}
-    # accuracy of GPU steps against the exact step, 32^3 Q_4, Q = 4, tau = 5e-4
-    na, Qa = 32, 4
+    acc = accuracy_leg(torch, R, 32, k, Q, tau)
+    acc64 = accuracy_leg(torch, R, 64, k, Q, tau)
+    return cpu, acc, acc64
+
+
+def accuracy_leg(torch, R, na, k=4, Qa=4, tau=5e-4):
+    """Error of one GPU step (seeded Fourier data, every form and FGMRES
+    tolerance) against the oracle's exact modal step on the na^3 Q_k grid."""
+    import numpy as np
+    from oracle.step import ModalSolver
+    from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
     Na = na * k + 1
     inner = lambda v: v.reshape(Na, Na, Na)[1:-1, 1:-1, 1:-1].reshape(-1)
-    s = R.RadauIIA(na, k, Qa, tau)
+    s = R.RadauIIA(na, k, Qa, tau, autotune=0)
     x1 = grid_coords(s.info["nodes"], na)
     s.close()
     y0 = fourier_field(x1, seed=0)
     t0 = time.perf_counter()
     ref = ModalSolver(na, k).step(RadauIIA(Qa), tau, inner(y0))
     t_oracle = time.perf_counter() - t0
-    acc = {"grid": "32^3 cells Q_4, Q=4, tau=5e-4, same seeded data", "oracle_modal_step_s": t_oracle,
+    acc = {"grid": f"{na}^3 cells Q_{k}, Q={Qa}, tau={tau:g}, same seeded data", "oracle_modal_step_s": t_oracle,
            "mixed_batched": {}, "fp64_per_stage": {}, "complex_presb_mixed_batched": {}}
     for name, prec, mode, method, rtols in (
             ("mixed_batched", R.RK_PREC_MIXED, R.RK_BATCHED, R.RK_METHOD_CROUT, RTOLS),
@@ -248,7 +260,10 @@ def cpu_baseline_leg(torch, R, n=16, k=4, Q=4, tau=5e-4, budget_s=12.0):
             err = float(np.linalg.norm(inner(y.cpu().numpy()) - ref) / np.linalg.norm(ref))
             acc[name][f"{rtol:.0e}"] = {"rel_l2_error": err, "fgmres_iterations": st["iterations"]}
             s.close()
-    return cpu, acc
+            del y
+    del ref, y0
+    torch.cuda.empty_cache()
+    return acc
 
 
 BATCH_CELLS = (4, 6, 8, 12, 16, 24, 32, 48)
@@ -352,10 +367,12 @@ def deformed_step_leg(torch, R, y0, n=64, k=4, Q=4, tau=5e-4, eps=0.05, steps=3)
     return out
 
 
-def loosest_rtol(acc_runs, bound=1e-8):
-    """The loosest FGMRES tolerance whose step error is within `bound`."""
-    ok = [float(r) for r, v in acc_runs.items() if v["rel_l2_error"] <= bound]
-    return max(ok) if ok else min(float(r) for r in acc_runs)
+def loosest_rtol(*acc_runs, bound=1e-8):
+    """The loosest FGMRES tolerance whose step error is within `bound` on
+    every grid given (dicts tolerance -> run)."""
+    rtols = set(acc_runs[0])
+    ok = [float(r) for r in rtols if all(runs[r]["rel_l2_error"] <= bound for runs in acc_runs)]
+    return max(ok) if ok else min(float(r) for r in rtols)
 
 
 def main():
@@ -470,12 +487,12 @@ def main():
               "block_iterations": blk, "vcycle_sequences": vcs_cx}
         log(f"[bench] complex PRESB: {t_cx * 1e3:.2f} ms/step, block its {blk[-1]}")
     at_acc = None
-    cpu = acc = None
+    cpu = acc = acc64 = None
     if not args.no_cpu:
-        log("[bench] host leg: cpu baseline and accuracy against the oracle on 32^3")
-        cpu, acc = cpu_baseline_leg(torch, R)
-        r_mixed = loosest_rtol(acc["mixed_batched"])
-        r_plain = loosest_rtol(acc["fp64_per_stage"])
+        log("[bench] host leg: cpu baseline and accuracy against the oracle on 32^3 and 64^3")
+        cpu, acc, acc64 = cpu_baseline_leg(torch, R)
+        r_mixed = loosest_rtol(acc["mixed_batched"], acc64["mixed_batched"])
+        r_plain = loosest_rtol(acc["fp64_per_stage"], acc64["fp64_per_stage"])
         tm, im, _ = time_steps(torch, R, n, k, Q, tau, args.steps, 1, y0, rtol=r_mixed, **mixed)
         at_acc = {"bound": 1e-8, "mixed_batched": {"rtol": r_mixed, "ms_per_step": tm * 1e3, "fgmres_iterations": im}}
         log(f"[bench] at 1e-8 accuracy: mixed batched {tm * 1e3:.2f} ms (rtol {r_mixed:.0e})")
@@ -485,7 +502,7 @@ def main():
             at_acc["speedup"] = tp / tm
             log(f"[bench] at 1e-8 accuracy: plain fp64 per-stage {tp * 1e3:.2f} ms (rtol {r_plain:.0e})")
         if not args.no_complex:
-            r_cx = loosest_rtol(acc["complex_presb_mixed_batched"])
+            r_cx = loosest_rtol(acc["complex_presb_mixed_batched"], acc64["complex_presb_mixed_batched"])
             blk = []
             tc, ic, _ = time_steps(torch, R, n, k, Q, tau, args.steps, 1, y0, blocks=blk, rtol=r_cx,
                                    method=R.RK_METHOD_COMPLEX, **mixed)
@@ -560,6 +577,7 @@ def main():
     }
     if cpu is not None:
         out["accuracy_vs_oracle"] = acc
+        out["accuracy_vs_oracle_64cubed"] = acc64
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <thread>
 #include <vector>
@@ -757,46 +758,52 @@ int time_launches(rk_ctx* c, int reps, F&& fn, float* ms) {
 // The tile autotuner: per level, the z-chunk length of the diagonal-mix
 // operator in the preconditioner precision (on the level's buffers, with the
 // V-cycle's stage count), and for the fine-level fp64 pair operator of the
-// Krylov method; candidates 1, 2, 4, 8, 16 elements, each timed twice over
-// four launches (interleaved), the fastest average wins.  The operator's
-// results do not depend on the choice (the work decomposition changes, the
-// arithmetic of every output does not).
+// Krylov method.  Candidates 1, 2, 4, 8, 16 elements are timed in three
+// interleaved rounds of four launches each, after untimed launches that bring
+// the clocks up; the candidate with the lowest mean over its rounds wins (a
+// single lucky round does not).  The operator's results do not depend on the
+// choice (the work decomposition changes, the arithmetic of every output
+// does not).
+int pick_chunk(rk_ctx* c, int* cz_slot, const std::function<int()>& launch) {
+    static const int cand[] = {1, 2, 4, 8, 16};
+    constexpr int nc = 5, rounds = 3;
+    float sum[nc] = {};
+    *cz_slot = 0;                                    // warm-up with the size heuristic
+    for (int i = 0; i < 8; ++i)
+        if (int rc = launch()) return rc;
+    for (int r = 0; r < rounds; ++r)
+        for (int i = 0; i < nc; ++i) {
+            *cz_slot = cand[i];
+            float ms = 0.f;
+            if (int rc = time_launches(c, 4, launch, &ms)) return rc;
+            sum[i] += ms;
+        }
+    int pick = 0;
+    for (int i = 1; i < nc; ++i)
+        if (sum[i] < sum[pick]) pick = i;
+    *cz_slot = cand[pick];
+    return RK_OK;
+}
+
 int autotune(rk_ctx* c) {
-    static const int cand[] = {1, 2, 4, 8, 16, 1, 2, 4, 8, 16};
     const int ns = c->opt.mode == RK_BATCHED ? c->Q : 1;
     for (size_t l = 0; l < c->lv.size() && !c->dmg; ++l) {
         Level& L = c->lv[l];
         HIPCHK(c, launch_random_fill(c->pc, L.x, L.N, c->Q, 777u + (unsigned)l, c->stream));
-        float best = 0.f;
-        int pick = 0;
-        for (int cz : cand) {
-            L.cz = cz;
-            float ms = 0.f;
-            int rc = time_launches(c, 4, [&] {
-                return op(c, c->k, c->pc, EPI_STORE, L.blk, L.x, L.y, nullptr, nullptr, L.n, 0, ns, 0, 0);
-            }, &ms);
-            if (rc) return rc;
-            if (pick == 0 || ms < best) { best = ms; pick = cz; }
-        }
-        L.cz = pick;
+        int rc = pick_chunk(c, &L.cz, [&] {
+            return op(c, c->k, c->pc, EPI_STORE, L.blk, L.x, L.y, nullptr, nullptr, L.n, 0, ns, 0, 0);
+        });
+        if (rc) return rc;
     }
     // fine-level fp64 pair operator (mass input in mbuf, stiffness input in w)
     HIPCHK(c, launch_random_fill(RK_FP64, c->mbuf, c->N, c->Q, 4242u, c->stream));
     HIPCHK(c, launch_random_fill(RK_FP64, c->w, c->N, c->Q, 4243u, c->stream));
     if (!c->deformed) {
-        float best = 0.f;
-        int pick = 0;
-        for (int cz : cand) {
-            c->cz_pair = cz;
-            float ms = 0.f;
-            int rc = time_launches(c, 4, [&] {
-                return op(c, c->k, RK_FP64, EPI_STORE, c->form[F_CALA], c->mbuf, c->kv, nullptr, nullptr, c->n, 0,
-                          c->Q, 0, 0, c->w);
-            }, &ms);
-            if (rc) return rc;
-            if (pick == 0 || ms < best) { best = ms; pick = cz; }
-        }
-        c->cz_pair = pick;
+        int rc = pick_chunk(c, &c->cz_pair, [&] {
+            return op(c, c->k, RK_FP64, EPI_STORE, c->form[F_CALA], c->mbuf, c->kv, nullptr, nullptr, c->n, 0, c->Q,
+                      0, 0, c->w);
+        });
+        if (rc) return rc;
     }
     return RK_OK;
 }
