@@ -176,3 +176,32 @@ def test_full_size_32cubed_q4_batched(R, Q, prec, bar):
     print(f"32^3 batched Q={Q} {prec}: its={stats['iterations']} err={err:.3e}", flush=True)
     assert err <= bar
     solver.close()
+
+
+def test_full_size_64cubed_q4_mixed_batched(R):
+    """The benchmark workload itself: 64^3 cells, Q_4 (257^3 nodes), Q = 4,
+    tau = 5e-4, mixed precision, batched stages, one step of the seeded
+    Fourier data against the modal oracle at rtol 1e-10 and at rtol 1e-6 (the
+    tolerance the benchmark uses for 1e-8 accuracy): error within 1e-8."""
+    from oracle.step import ModalSolver
+    from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
+    n, k, Q, tau = 64, 4, 4, 5e-4
+    N = n * k + 1
+    inner = lambda v: v.reshape(N, N, N)[1:-1, 1:-1, 1:-1].reshape(-1)
+    y0 = None
+    ref = None
+    for rtol in (1e-10, 1e-6):
+        print(f"64^3 mixed batched rtol={rtol:g}", flush=True)
+        solver = R.RadauIIA(n, k, Q, tau, mode=R.RK_BATCHED, precision=R.RK_PREC_MIXED, rtol=rtol)
+        if y0 is None:
+            y0 = fourier_field(grid_coords(solver.info["nodes"], n), seed=0)
+            ref = ModalSolver(n, k).step(RadauIIA(Q), tau, inner(y0))
+        y = torch.tensor(y0, device="cuda")
+        stats = solver.step(0.0, y)
+        err = _rel(inner(y.cpu().numpy()), ref)
+        print(f"64^3 mixed batched rtol={rtol:g}: its={stats['iterations']} err={err:.3e}", flush=True)
+        assert err <= 1e-8
+        solver.close()
+        del y
+        torch.cuda.empty_cache()
