@@ -34,6 +34,8 @@ Reported:
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        python bench.py --mode op [--op-reps R]      (operator launches + one
            device copy of the same size, for counter runs)
+       python bench.py --mode deformed [--op-reps R]   (the same for the
+           deformed-mesh operator, Q = 4)
        python bench.py --traffic-from FETCH.csv WRITE.csv   (turn two
            rocprofv3 --pmc runs of --mode op into the committed traffic record)
 """
@@ -390,8 +392,9 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--cheb-degree", type=int, default=None, help="smoother degree (library default if unset)")
     ap.add_argument("--cheb-range", type=float, default=None, help="Chebyshev range (library default if unset)")
-    ap.add_argument("--mode", choices=["full", "op"], default="full",
-                    help="op: only the batched fp32 block operator launches (for counter runs)")
+    ap.add_argument("--mode", choices=["full", "op", "deformed"], default="full",
+                    help="op: only the batched fp32 block operator launches; deformed: only the "
+                         "deformed-mesh operator (both for counter runs)")
     ap.add_argument("--cz", type=int, default=None, help="z-chunk length of the counter runs (--traffic-from)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic record from two rocprofv3 --pmc runs of --mode op")
@@ -431,6 +434,20 @@ def main():
                           "level_cz": solver.info["level_cz"][0], "RK_OP_CZ": os.environ.get("RK_OP_CZ"),
                           "reps": args.op_reps, "GBps": 8.0 * Q * N ** 3 / t_blk / 1e9,
                           "copy_bytes": u32.numel() * 4}), flush=True)
+        return 0
+    if args.mode == "deformed":
+        # the deformed-mesh operator at Q stages (fp32, eps = 0.05) and one
+        # plain device copy of the same size, for counter runs
+        op = R.DeformedOperator(n, k, 0.05, dtype=torch.float32)
+        u = torch.randn(Q * N ** 3, dtype=torch.float32, device="cuda")
+        v = torch.empty_like(u)
+        for _ in range(args.op_reps):
+            op.apply(u, v, [2.0] * Q, [5e-4] * Q)
+        v.copy_(u)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "deformed", "kernel": "deformed_op_kernel<4, float, false>", "Q": Q,
+                          "applies": args.op_reps, "launches_per_apply": 8, "copy_bytes": u.numel() * 4,
+                          "geometry_bytes": op.geometry.numel() * 4}), flush=True)
         return 0
     smoother = {}
     if args.cheb_degree is not None:
