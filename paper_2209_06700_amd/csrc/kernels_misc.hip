@@ -157,6 +157,44 @@ __global__ void __launch_bounds__(kBlock) stage_mix_kernel(const Tin* __restrict
     }
 }
 
+// The same mix for qin = qout = Q known at compile time: the coefficients
+// stay in registers, one thread per node, the plane index from the grid's y
+// dimension and 32-bit in-plane indexing (N^2 < 2^31).
+template <typename Tin, typename Tout, int Q, bool TWO>
+__global__ void __launch_bounds__(kBlock) stage_mix_q_kernel(const Tin* __restrict__ in, Tout* __restrict__ out,
+                                                             const double* __restrict__ D, int N,
+                                                             double* __restrict__ out2,
+                                                             const double* __restrict__ D2,
+                                                             const double* __restrict__ in_scale,
+                                                             SlotIdx sidx) {
+    const int z = blockIdx.y;
+    const unsigned NN = (unsigned)N * (unsigned)N;
+    const unsigned t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= NN) return;
+    const unsigned y = t / (unsigned)N, x = t - y * (unsigned)N;
+    const int nK = N - 1;
+    const bool inner = x > 0 && (int)x < nK && y > 0 && (int)y < nK && z > 0 && z < nK;
+    const long long N3 = (long long)NN * N;
+    const long long r = (long long)z * NN + t;
+    double u[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const double sc = in_scale ? in_scale[sidx.v[j]] : 1.0;
+        u[j] = inner ? sc * (double)in[(long long)j * N3 + r] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        double acc = 0.0, acc2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            acc = fma(D[i * Q + j], u[j], acc);
+            if (TWO) acc2 = fma(D2[i * Q + j], u[j], acc2);
+        }
+        out[(long long)i * N3 + r] = (Tout)acc;
+        if (TWO) out2[(long long)i * N3 + r] = acc2;
+    }
+}
+
 // out_i = c1_i G + c2_i w on interior nodes, 0 on boundary nodes (the load
 // vector's boundary entries belong to eliminated Dirichlet unknowns).
 __global__ void __launch_bounds__(kBlock) rhs_mix_kernel(const double* __restrict__ G, const double* __restrict__ w,
@@ -543,6 +581,12 @@ hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* 
     return hipGetLastError();
 }
 
+// f(integral_constant<int, q>) for q in 1..RK_MAX_Q
+template <typename F>
+hipError_t dispatch_q(int q, F&& f) {
+    return dispatch_nv_impl(q, f, std::make_integer_sequence<int, RK_MAX_Q>{});
+}
+
 hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* out, const double* D,
                             int qout, int qin, int N, hipStream_t st, double* out2, const double* D2,
                             const double* in_scale, const SlotIdx* scale_idx) {
@@ -550,6 +594,28 @@ hipError_t launch_stage_mix(int dtype_in, const void* in, int dtype_out, void* o
     dim3 g(grid_for(N3)), b(kBlock);
     SlotIdx sidx;
     for (int j = 0; j < RK_MAX_Q; ++j) sidx.v[j] = scale_idx ? scale_idx->v[j] : 0;
+    if (qin == qout && (long long)N * N < (1ll << 31) && N <= 65535) {
+        const dim3 gq((unsigned)(((long long)N * N + kBlock - 1) / kBlock), (unsigned)N);
+        hipError_t e = dispatch_q(qin, [&](auto QC) {
+            constexpr int QQ = decltype(QC)::value;
+            auto go = [&](auto tin, auto tout) {
+                using Ti = decltype(tin);
+                using To = decltype(tout);
+                if (out2)
+                    stage_mix_q_kernel<Ti, To, QQ, true><<<gq, b, 0, st>>>((const Ti*)in, (To*)out, D, N, out2, D2,
+                                                                           in_scale, sidx);
+                else
+                    stage_mix_q_kernel<Ti, To, QQ, false><<<gq, b, 0, st>>>((const Ti*)in, (To*)out, D, N, out2,
+                                                                            D2, in_scale, sidx);
+            };
+            if (dtype_in == RK_FP64 && dtype_out == RK_FP64) go(double{}, double{});
+            else if (dtype_in == RK_FP64) go(double{}, float{});
+            else if (dtype_out == RK_FP64) go(float{}, double{});
+            else go(float{}, float{});
+            return hipGetLastError();
+        });
+        return e;
+    }
     if (dtype_in == RK_FP64 && dtype_out == RK_FP64)
         stage_mix_kernel<double, double><<<g, b, 0, st>>>((const double*)in, (double*)out, D, qout, qin, N, out2, D2, in_scale, sidx);
     else if (dtype_in == RK_FP64 && dtype_out == RK_FP32)
