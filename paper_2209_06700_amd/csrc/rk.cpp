@@ -1169,8 +1169,19 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
     if (c->opt.autotune && (rc = autotune(c))) {
         g_create_error = c->err; delete c; return rc;
     }
-    e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) { delete c; return fail(nullptr, RK_EHIP, hipGetErrorString(e)); }
+    // the private streams and events of split V-cycles, made here rather
+    // than on first use (which may fall inside a graph capture)
+    const int groups = c->opt.mode == RK_BATCHED ? std::min(c->opt.vc_streams, c->Q) : 1;
+    if (groups >= 2) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    for (int g = 1; g < groups && e == hipSuccess; ++g) {
+        e = hipStreamCreateWithFlags(&c->aux_stream[g], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[g], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        rk_destroy(c);
+        return fail(nullptr, RK_EHIP, hipGetErrorString(e));
+    }
     *out = c;
     return RK_OK;
 }
