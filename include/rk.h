@@ -148,7 +148,12 @@ typedef struct {
                                    (forked from and joined back into the context's
                                    stream), so that the latency-bound coarse levels
                                    of one group overlap the fine levels of another.
-                                   Results do not depend on it.                      */
+                                   Applies to V-cycles of at least 2^23 fine-level
+                                   stage-DoFs; smaller ones run on one stream.
+                                   Results do not depend on it.  Opt-in (default
+                                   1): with many contexts replaying split graphs
+                                   at once, slow or failed convergence was seen
+                                   and is not explained.                             */
 } rk_options;
 
 typedef struct {
@@ -187,7 +192,7 @@ typedef struct {
 /* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
    max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
    cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0,
-   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1, vc_streams 2. */
+   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1, vc_streams 1. */
 void rk_default_options(rk_options* opt);
 
 /* Bytes of device workspace needed for the given mesh, degree (1..6),

@@ -45,6 +45,11 @@ hipError_t launch_op(const OpLaunch& L) {
 namespace {
 
 constexpr int kRedBlocks = 2048;     // blocks of the reduction kernels
+// Split V-cycles only from this many fine-level stage-DoFs per V-cycle on:
+// smaller V-cycles are latency-bound on every level, and two branches of
+// them gain nothing (when many contexts share the hardware queues, the
+// branches can even serialise).
+constexpr long long kSplitMin = 1ll << 23;
 // slots (x 81 doubles) of the device Q x Q mixing data
 constexpr int kMixSinv = 0, kMixS = 81, kMixRhs = 162, kMixAinvS = 243, kMixAinv = 324, kMixA = 405;
 // direct diagonalisation: Lam_r, PRESB input and output mixes, Lam_r times the output mix
@@ -567,7 +572,7 @@ int vcycle_range(rk_ctx* c, const void* b, void* x, void* scratch, int s0, int n
     const bool res_first = single && (c->opt.coarse_cheb_degree % 2 == 1);
     void* first = res_first ? x : scratch;
     void* second = res_first ? scratch : x;
-    const int ng = std::min(c->opt.vc_streams, ns);
+    const int ng = c->N3 * ns >= kSplitMin ? std::min(c->opt.vc_streams, ns) : 1;
     if (ng >= 2 && c->opt.mode == RK_BATCHED) {
         if (!c->ev_fork) HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
@@ -1051,7 +1056,7 @@ void rk_default_options(rk_options* o) {
     o->deform = 0.0;
     o->autotune = 1;
     o->deform_mg = 1;
-    o->vc_streams = 2;
+    o->vc_streams = 1;
 }
 
 int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {
@@ -1171,7 +1176,8 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
     }
     // the private streams and events of split V-cycles, made here rather
     // than on first use (which may fall inside a graph capture)
-    const int groups = c->opt.mode == RK_BATCHED ? std::min(c->opt.vc_streams, c->Q) : 1;
+    const int groups = c->opt.mode == RK_BATCHED && c->N3 * c->Q >= kSplitMin ? std::min(c->opt.vc_streams, c->Q)
+                                                                          : 1;
     if (groups >= 2) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     for (int g = 1; g < groups && e == hipSuccess; ++g) {
         e = hipStreamCreateWithFlags(&c->aux_stream[g], hipStreamNonBlocking);
