@@ -150,10 +150,9 @@ typedef struct {
                                    of one group overlap the fine levels of another.
                                    Applies to V-cycles of at least 2^23 fine-level
                                    stage-DoFs; smaller ones run on one stream.
-                                   Results do not depend on it.  Opt-in (default
-                                   1): with many contexts replaying split graphs
-                                   at once, slow or failed convergence was seen
-                                   and is not explained.                             */
+                                   Results do not depend on it.  Contexts stepped
+                                   concurrently (rk_step_batch) already fill the
+                                   GPU; there 1 is faster.                           */
 } rk_options;
 
 typedef struct {
@@ -192,7 +191,7 @@ typedef struct {
 /* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
    max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
    cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0,
-   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1, vc_streams 1. */
+   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1, vc_streams 2. */
 void rk_default_options(rk_options* opt);
 
 /* Bytes of device workspace needed for the given mesh, degree (1..6),

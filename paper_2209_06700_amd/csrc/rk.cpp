@@ -47,8 +47,7 @@ namespace {
 constexpr int kRedBlocks = 2048;     // blocks of the reduction kernels
 // Split V-cycles only from this many fine-level stage-DoFs per V-cycle on:
 // smaller V-cycles are latency-bound on every level, and two branches of
-// them gain nothing (when many contexts share the hardware queues, the
-// branches can even serialise).
+// them gain nothing.
 constexpr long long kSplitMin = 1ll << 23;
 // slots (x 81 doubles) of the device Q x Q mixing data
 constexpr int kMixSinv = 0, kMixS = 81, kMixRhs = 162, kMixAinvS = 243, kMixAinv = 324, kMixA = 405;
@@ -142,7 +141,8 @@ struct rk_ctx {
     Coeffs form[F_NFORMS];         // fine-level operator coefficients
     Coeffs presb_m;                // PRESB coupling: Im(lam_j) M on slots nb + j
     int cz_pair = 0;               // tuned z-chunk of the fine-level fp64 pair operator
-    void* tmp = nullptr;           // restriction intermediate
+    void* tmp = nullptr;           // restriction intermediate, [Q][tmp_stage]
+    size_t tmp_stage = 0;          // its per-stage size: the largest N_l N_(l+1)^2
     long long ld = 0;              // stride of the Krylov vectors (Q N3 padded to 256 bytes)
     double* V = nullptr;           // (restart+1) x ld
     double* Z = nullptr;           // restart x ld
@@ -257,6 +257,7 @@ size_t carve(rk_ctx& c, char* base) {
     size_t tmp = 1;
     for (size_t l = 0; l + 1 < c.lv.size(); ++l)
         tmp = std::max(tmp, (size_t)c.lv[l].N * c.lv[l + 1].N * c.lv[l + 1].N);
+    c.tmp_stage = tmp;
     c.tmp = cv.take(pcs * Q * tmp);
     const long long qn = (long long)Q * c.N3;
     const int m = c.opt.restart;
@@ -512,8 +513,9 @@ int restrict_to(rk_ctx* c, int l, int s0, int ns, const void* fine) {
     Level& F = c->lv[l];
     Level& C = c->lv[l + 1];
     const size_t es = dsize(c->pc);
-    // the intermediate holds N_f N_c^2 values per stage; stages at their own offsets
-    void* tmp = (char*)c->tmp + es * s0 * ((size_t)F.N * C.N * C.N);
+    // stage s owns tmp[s * tmp_stage ...] on every level, so that groups of
+    // stages restricting on different levels at once never overlap
+    void* tmp = (char*)c->tmp + es * s0 * c->tmp_stage;
     HIPCHK(c, launch_restrict(c->k, c->pc, (const char*)fine + es * s0 * F.N3, (char*)C.b + es * s0 * C.N3,
                               tmp, C.n, ns, F.N3, C.N3, c->stream));
     return RK_OK;
@@ -1056,7 +1058,7 @@ void rk_default_options(rk_options* o) {
     o->deform = 0.0;
     o->autotune = 1;
     o->deform_mg = 1;
-    o->vc_streams = 1;
+    o->vc_streams = 2;
 }
 
 int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {

@@ -228,6 +228,31 @@ def test_results_do_not_depend_on_the_stream_split(R, method):
         assert torch.equal(val[0], ref[0]) and torch.equal(val[1], ref[1]) and val[2] == ref[2], key
 
 
+def test_split_vcycles_in_steps_of_a_large_problem(R):
+    """Regression: 48^3 cells Q_5, Q = 5 (blocks in groups of 3 and 2), tuned
+    tiles, restart 20.  Split V-cycles once shared the restriction's
+    intermediate buffer between groups working on different levels at the
+    same time (its per-stage offset depended on the level); steps then took
+    200 iterations.  The split step must equal the one-stream step bitwise,
+    graph-replayed and eager."""
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
+    n, k, Q, tau = 48, 5, 5, 8.6e-4
+    outs = {}
+    for vs, timing in ((1, 0), (2, 0), (2, 1)):
+        s = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, restart=20, vc_streams=vs, timing=timing)
+        y = torch.tensor(fourier_field(grid_coords(s.info["nodes"], n), seed=1), device="cuda")
+        its = s.step(0.0, y)["iterations"]
+        torch.cuda.synchronize()
+        outs[(vs, timing)] = (y.cpu(), its)
+        print(f"48^3 Q_5 vc_streams={vs} timing={timing}: its {its}", flush=True)
+        s.close()
+        del y
+        torch.cuda.empty_cache()
+    ref = outs[(1, 0)]
+    for key, (y, its) in outs.items():
+        assert its == ref[1] and torch.equal(y, ref[0]), key
+
+
 def test_autotune_picks_valid_chunks(R):
     from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
     n, k, Q, tau = 16, 3, 3, 0.01
