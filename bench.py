@@ -276,8 +276,10 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20, autotune=1):
     each, drawn with numpy.random.default_rng(seed): n^3 cells with n from
     4..48 (values with a multigrid hierarchy: n = 2^j or 3 * 2^j), degree
     U{1..6}, Q U{1..5}, tau log-uniform in [1e-4, 1e-1], mixed precision,
-    seeded Fourier data.  Timed once concurrently (rk_step_batch, one stream
-    and host thread per group of problems) and once one problem after another."""
+    seeded Fourier data.  The problems are spread over the streams by load
+    (largest first, each onto the stream with the fewest stage-DoFs so far).
+    Timed once concurrently (rk_step_batch, one host thread per stream) and
+    once one problem after another."""
     import numpy as np
     from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
     rng = np.random.default_rng(seed)
@@ -289,10 +291,18 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20, autotune=1):
         tau = float(10 ** rng.uniform(-4, -1))
         probs.append((n, k, Q, tau))
     sts = [torch.cuda.Stream() for _ in range(streams)]
+    # streams by load: problems largest first (stage-DoFs), each onto the
+    # stream with the fewest stage-DoFs so far
+    sdof = [Q * (n * k + 1) ** 3 for n, k, Q, _ in probs]
+    load, sid = [0] * streams, [0] * count
+    for i in sorted(range(count), key=lambda i: -sdof[i]):
+        s = min(range(streams), key=lambda j: load[j])
+        sid[i] = s
+        load[s] += sdof[i]
     # one V-cycle stream per context (vc_streams = 1): the concurrent
     # contexts already fill the GPU, and split V-cycles measured slower here
     ctxs = [R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, rtol=1e-10, restart=restart,
-                       autotune=autotune, vc_streams=1, stream=sts[i % streams])
+                       autotune=autotune, vc_streams=1, stream=sts[sid[i]])
             for i, (n, k, Q, tau) in enumerate(probs)]
     y0 = [torch.tensor(fourier_field(grid_coords(c.info["nodes"], n), seed=i), device="cuda")
           for i, (c, (n, _, _, _)) in enumerate(zip(ctxs, probs))]
@@ -318,7 +328,7 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20, autotune=1):
     torch.cuda.empty_cache()
     return {"problems": count, "recipe": f"default_rng({seed}): n in {list(BATCH_CELLS)}, k U{{1..6}}, "
                                          f"Q U{{1..5}}, tau log-uniform [1e-4, 1e-1], mixed, rtol 1e-10, vc_streams 1, "
-                                         f"restart {restart}",
+                                         f"restart {restart}, streams assigned by load",
             "stage_dofs": sdofs, "streams": streams, "autotune": autotune, "s_concurrent": t_conc,
             "s_sequential": t_seq,
             "speedup": t_seq / t_conc, "stage_dof_steps_per_s": sdofs / t_conc,

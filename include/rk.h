@@ -234,10 +234,11 @@ int rk_step(rk_ctx* ctx, double t_n, double* d_y, const double* d_G, const doubl
    Entry i is rk_step(ctx[i], t_n[i], d_y[i], d_G[i], h_gamma + i*RK_MAX_Q,
    h_stats + i); d_G may be NULL or hold NULL entries, h_stats and h_codes may
    be NULL.  The entries run concurrently on `threads` host threads (0: one
-   per entry; at most 16): worker w steps entries w, w + threads, ... in
-   order, each on its context's own stream, so entries created on different
-   streams overlap on the GPU (give entry i the stream i mod threads).  A
-   context must appear at most once.  Every entry is attempted; per-entry codes
+   per entry; at most 16), each on its context's own stream, so entries on
+   different streams overlap on the GPU.  Entries whose contexts share a
+   stream run on one thread, in input order; the streams are handed to the
+   threads largest first (by the stage-DoFs N^3 Q of their contexts), each
+   to the least loaded thread.  A context must appear at most once.  Every entry is attempted; per-entry codes
    go to h_codes, and the return value is the first failing entry's code
    (RK_OK if all succeeded).  Errors of an entry are reported by
    rk_last_error(ctx[i]). */

@@ -1361,10 +1361,32 @@ int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* cons
     int nt = threads > 0 ? threads : count;
     nt = std::max(1, std::min(std::min(nt, count), 16));
     std::vector<int> rc(count, RK_OK);
-    // worker w steps entries w, w + nt, ... in order (contexts that share a
-    // stream should share a worker: give entry i the stream i mod nt)
+    // Entries are grouped by their context's stream (contexts that share a
+    // stream run on one worker, in input order).  The streams go to the
+    // workers largest first, each to the least loaded worker, by the
+    // stage-DoFs of their contexts.
+    std::vector<hipStream_t> streams;
+    std::vector<std::vector<int>> members;
+    std::vector<double> cost;
+    for (int i = 0; i < count; ++i) {
+        size_t s = 0;
+        while (s < streams.size() && streams[s] != ctx[i]->stream) ++s;
+        if (s == streams.size()) { streams.push_back(ctx[i]->stream); members.emplace_back(); cost.push_back(0.0); }
+        members[s].push_back(i);
+        cost[s] += (double)ctx[i]->N3 * ctx[i]->Q;
+    }
+    std::vector<int> order(streams.size());
+    for (size_t s = 0; s < order.size(); ++s) order[s] = (int)s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<std::vector<int>> plan(nt);
+    std::vector<double> load(nt, 0.0);
+    for (int s : order) {
+        const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[w] += cost[s];
+        plan[w].insert(plan[w].end(), members[s].begin(), members[s].end());
+    }
     auto work = [&](int w) {
-        for (int i = w; i < count; i += nt) {
+        for (int i : plan[w]) {
             if (hipSetDevice(ctx[i]->device) != hipSuccess) { rc[i] = fail(ctx[i], RK_EHIP, "hipSetDevice failed"); continue; }
             rc[i] = rk_step(ctx[i], t_n[i], y[i], G ? G[i] : nullptr, gamma ? gamma + (size_t)i * RK_MAX_Q : nullptr,
                             stats ? stats + i : nullptr);
