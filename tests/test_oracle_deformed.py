@@ -97,6 +97,43 @@ def test_sampled_rows_equal_assembled_rows():
     np.testing.assert_allclose(kk, (K @ u)[rows], atol=1e-12)
 
 
+
+@pytest.mark.parametrize("n,k", [(2, 2), (3, 3)])
+def test_sampled_absolute_rows_bound_and_single_cell_equality(n, k):
+    """The |M_e| |u| bound of the sampled rows (rounding tolerances of the
+    deformed-operator tests) is at least |M| |u| of the assembled deformed
+    matrices everywhere, and equal to it at nodes inside a single cell, where
+    no two cells add into the row."""
+    eps = 0.08
+    mesh = Mesh(n, k)
+    M, K = assemble(mesh, eps)
+    u = np.random.default_rng(7).standard_normal(mesh.ndofs)
+    u[~mesh.interior_mask()] = 0
+    au = np.abs(u)
+    N = mesh.N
+    g1 = range(1, N - 1)
+    allint = [(a, b, c) for c in g1 for b in g1 for a in g1]
+    inner = [(a, b, c) for (a, b, c) in allint if a % k and b % k and c % k]
+    for nodes in (allint, inner):
+        m, kk = sampled_rows(n, k, eps, au, nodes, absolute=True)
+        rows = [a + N * (b + N * c) for a, b, c in nodes]
+        Ma, Ka = (abs(M) @ au)[rows], (abs(K) @ au)[rows]
+        if nodes is inner:
+            np.testing.assert_allclose(m, Ma, rtol=1e-13)
+            np.testing.assert_allclose(kk, Ka, rtol=1e-13)
+        else:
+            assert np.all(m >= Ma * (1 - 1e-13)) and np.all(kk >= Ka * (1 - 1e-13))
+            assert np.all(Ma >= np.abs(M @ u)[rows] * (1 - 1e-13))
+            assert np.all(Ka >= np.abs(K @ u)[rows] * (1 - 1e-13))
+    # Q_1 element mass entries are all positive: no cancellation anywhere
+    mesh1 = Mesh(3, 1)
+    M1, _ = assemble(mesh1, eps)
+    u1 = np.abs(np.random.default_rng(8).standard_normal(mesh1.ndofs))
+    u1[~mesh1.interior_mask()] = 0
+    nodes1 = [(1, 1, 1), (2, 1, 2), (1, 2, 1), (2, 2, 2)]
+    m1, _ = sampled_rows(3, 1, eps, u1, nodes1, absolute=True)
+    np.testing.assert_allclose(m1, (abs(M1) @ u1)[[a + 4 * (b + 4 * c) for a, b, c in nodes1]], rtol=1e-13)
+
 def test_deformed_hierarchy_nested_and_affine_limit():
     """eps = 0 gives the affine hierarchy.  With eps != 0 the spaces stay
     nested (the same P), and the Galerkin product P^T M_f P differs from the

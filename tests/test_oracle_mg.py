@@ -73,10 +73,63 @@ def test_vcycle_contraction(mg8):
         assert rate < 0.3, (i, rate)
 
 
-def test_eig_bounds_are_upper_bounds(mg8):
+def _q1_max_eig_closed_form(n, lams, tau):
+    """Largest eigenvalue of D^-1 (lam M + tau K) over the blocks on the uniform
+    n^3 mesh of Q_1 elements, in closed form.  The 1D matrices m (mass) and a
+    (stiffness) are tridiagonal Toeplitz on the interior nodes, so the discrete
+    sine modes theta_d = j_d pi / n (j_d = 1..n-1) are eigenvectors of both,
+    with eigenvalues (h/3)(2 + cos theta) and (2/h)(1 - cos theta); the 3D
+    matrices are Kronecker sums of them and the Jacobi diagonal is constant,
+    (2h/3)^3 for M and 3 (2/h)(2h/3)^2 for K."""
+    h = 1.0 / n
+    th = np.arange(1, n) * np.pi / n
+    mu_m = (h / 3) * (2 + np.cos(th))
+    mu_a = (2 / h) * (1 - np.cos(th))
+    mz, my, mx = np.meshgrid(mu_m, mu_m, mu_m, indexing="ij")
+    az, ay, ax = np.meshgrid(mu_a, mu_a, mu_a, indexing="ij")
+    eM = mz * my * mx
+    eK = az * my * mx + mz * ay * mx + mz * my * ax
+    dM = (2 * h / 3) ** 3
+    dK = 3 * (2 / h) * (2 * h / 3) ** 2
+    return max(float(((l * eM + tau * eK) / (l * dM + tau * dK)).max()) for l in lams)
+
+
+@pytest.mark.parametrize("n,Q,tau", [(8, 3, 0.05), (24, 2, 1e-3), (6, 4, 0.7)])
+def test_max_eig_exact_q1_closed_form(n, Q, tau):
+    """Sec. 5.4 (one Chebyshev bound over all blocks): the oracle's largest
+    eigenvalue of D^-1 A over the blocks lam_i M + tau K equals the sine-mode
+    closed form on every level of a Q_1 hierarchy (the dense path for small
+    levels, the sparse eigensolver for 23^3 interior unknowns)."""
+    tab = RadauIIA(Q)
+    hier = Hierarchy(n, 1)
+    mg = BlockMG(hier, tab.lam, tau, degree=2, eig_max=[1.0] * hier.nlevels)
+    for l, m in enumerate(hier.sizes):
+        got = mg.max_eig_exact(l)
+        if m == 1:
+            assert got == 1.0          # no interior unknowns on one cell
+            continue
+        want = _q1_max_eig_closed_form(m, tab.lam, tau)
+        assert abs(got - want) <= 1e-9 * want, (l, m, got, want)
+
+
+def test_max_eig_exact_between_rayleigh_and_gershgorin(mg8):
+    """Q_2 (no closed form): the largest eigenvalue of D^-1 A lies above the
+    Rayleigh quotient v^T A v / v^T D v of any vector and below the largest
+    Gershgorin row sum of |D^-1 A|, for every block and level."""
     tab, hier, mg = mg8
+    rng = np.random.default_rng(3)
     for l in range(hier.nlevels):
-        assert mg.eig_max[l] >= mg.max_eig_exact(l) * 1.19
+        if hier.levels[l].M.shape[0] == 0:
+            continue
+        lam = mg.max_eig_exact(l)
+        ray = gersh = 0.0
+        for Ai, Di in zip(mg.A[l], mg.Dinv[l]):
+            for _ in range(5):
+                v = rng.standard_normal(Ai.shape[0])
+                ray = max(ray, (v @ (Ai @ v)) / (v @ (v / Di)))
+            gersh = max(gersh, float((abs(Ai).multiply(Di[:, None])).sum(axis=1).max()))
+        assert ray <= lam * (1 + 1e-12), (l, ray, lam)
+        assert lam <= gersh * (1 + 1e-12), (l, lam, gersh)
 
 
 def test_block_preconditioner_with_exact_blocks():
