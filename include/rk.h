@@ -298,6 +298,29 @@ int rk_deformed_geometry(const rk_mesh* mesh, int degree, double eps, int dtype,
 int rk_deformed_apply(const rk_mesh* mesh, int degree, int Q, const double* h_alpha, const double* h_beta,
                       int dtype, const void* d_geometry, const void* d_u, void* d_v, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * No allocation at all: for callers that cannot allocate device memory or
+ * create a context (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).
+ * ------------------------------------------------------------------------- */
+#define RK_STATIC_SCRATCH_BYTES (64u << 20)   /* per GPU, held until the process ends */
+
+/* v = op(u) as rk_apply_operator() computes it on a context created with
+   the same mesh, degree, Q and tau (Crout forms RK_OP_CALA, RK_OP_STAGE,
+   RK_OP_BLOCKS, RK_OP_K, RK_OP_M; affine mesh), but without a context: no
+   workspace, no allocation of any kind.  RK_OP_CALA and RK_OP_STAGE mix the
+   input stages first; the mixed input and the Q x Q table go to a static
+   device array of RK_STATIC_SCRATCH_BYTES (+ 4 KiB) that each GPU holds from
+   the first such call until the process ends, so those two forms need
+   Q * N^3 * sizeof(dtype) <= RK_STATIC_SCRATCH_BYTES and return RK_EINVAL
+   beyond it.  All calls on one GPU share that array: calls that overlap in
+   time on one GPU (two streams or two host threads) race and must be
+   serialised by the caller.  u and v are the caller's device vectors and must
+   not overlap.  Asynchronous on hip_stream (NULL = the default stream);
+   errors are reported by rk_last_error(NULL). */
+int rk_apply_operator_static(const rk_mesh* mesh, int degree, int Q, double tau, int form, int dtype,
+                             const void* d_u, void* d_v, void* hip_stream);
+
 /* Message of the last failed call on ctx (or of the last failed rk_create or
    context-free call when ctx is NULL).  The pointer stays valid until the
    next call. */

@@ -23,10 +23,12 @@ RK_METHOD_CROUT, RK_METHOD_COMPLEX = 0, 1
 RK_OP_CALA, RK_OP_STAGE, RK_OP_BLOCKS, RK_OP_K, RK_OP_M, RK_OP_CBLOCKS = 0, 1, 2, 3, 4, 5
 RK_MAX_Q, RK_MAX_DEGREE, RK_MAX_LEVELS = 9, 6, 16
 RK_MAX_DEFORM = 0.1
+RK_STATIC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = ["rk_default_options", "rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info",
            "rk_step", "rk_step_batch", "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner",
-           "rk_deformed_geometry_bytes", "rk_deformed_geometry", "rk_deformed_apply", "rk_last_error"]
+           "rk_deformed_geometry_bytes", "rk_deformed_geometry", "rk_deformed_apply", "rk_last_error",
+           "rk_apply_operator_static"]
 
 
 class rk_mesh(C.Structure):
@@ -87,11 +89,13 @@ def load():
     lib.rk_deformed_geometry.argtypes = [C.POINTER(rk_mesh), C.c_int, C.c_double, C.c_int, vp, vp]
     lib.rk_deformed_apply.argtypes = [C.POINTER(rk_mesh), C.c_int, C.c_int, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double), C.c_int, vp, vp, vp, vp]
+    lib.rk_apply_operator_static.argtypes = [C.POINTER(rk_mesh), C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                             vp, vp, vp]
     lib.rk_last_error.argtypes = [vp]
     lib.rk_last_error.restype = C.c_char_p
     for name in ("rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info", "rk_step", "rk_step_batch",
                  "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner", "rk_deformed_geometry_bytes",
-                 "rk_deformed_geometry", "rk_deformed_apply"):
+                 "rk_deformed_geometry", "rk_deformed_apply", "rk_apply_operator_static"):
         getattr(lib, name).restype = C.c_int
     return lib
 

@@ -1035,6 +1035,10 @@ int gmres(rk_ctx* c, rk_stats& st, bool& converged) {
 
 }  // namespace
 
+namespace rk {
+int report_free_error(int code, const std::string& msg) { return fail(nullptr, code, msg); }
+}  // namespace rk
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------

@@ -111,6 +111,10 @@ struct OpLaunch {
 };
 hipError_t launch_op(const OpLaunch& L);
 
+// Records msg as the message of a failed context-free call (rk_last_error(NULL))
+// and returns code.
+int report_free_error(int code, const std::string& msg);
+
 // Multigrid transfers (one fused pass each).
 // coarse = P^T fine for stages [0, nstage): fine grid of 2 nc cells (stage
 // stride fstride), coarse grid of nc cells (stride cstride), degree k; coarse

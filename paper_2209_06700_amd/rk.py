@@ -15,12 +15,13 @@ import torch
 from . import _lib
 from ._lib import (LIB, RK_BATCHED, RK_ENOCONV, RK_FP32, RK_FP64, RK_METHOD_COMPLEX, RK_METHOD_CROUT, RK_OK,
                    RK_OP_BLOCKS, RK_OP_CALA, RK_OP_CBLOCKS, RK_MAX_Q, RK_OP_K, RK_OP_M, RK_OP_STAGE,
-                   RK_PER_STAGE, RK_PREC_FP64, RK_PREC_MIXED, rk_info_t, rk_mesh, rk_options, rk_stats)
+                   RK_PER_STAGE, RK_PREC_FP64, RK_PREC_MIXED, RK_STATIC_SCRATCH_BYTES, rk_info_t, rk_mesh,
+                   rk_options, rk_stats)
 
 __all__ = ["RKError", "rk_default_options", "rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info",
            "rk_step", "rk_step_batch", "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner",
            "rk_last_error", "rk_deformed_geometry_bytes", "rk_deformed_geometry", "rk_deformed_apply",
-           "DeformedOperator",
+           "rk_apply_operator_static", "RK_STATIC_SCRATCH_BYTES", "DeformedOperator",
            "RadauIIA", "RK_FP64", "RK_FP32", "RK_PREC_FP64", "RK_PREC_MIXED", "RK_BATCHED",
            "RK_PER_STAGE", "RK_OP_CALA", "RK_OP_STAGE", "RK_OP_BLOCKS", "RK_OP_K", "RK_OP_M",
            "RK_OP_CBLOCKS", "RK_METHOD_CROUT", "RK_METHOD_COMPLEX"]
@@ -274,6 +275,19 @@ def rk_deformed_apply(n_cells: int, degree: int, alpha, beta, geometry: torch.Te
     b = (C.c_double * Q)(*[float(x) for x in beta])
     _check(LIB.rk_deformed_apply(C.byref(rk_mesh(n_cells)), degree, Q, a, b, _dtype_code(u),
                                  C.c_void_p(geometry.data_ptr()), up, vp, C.c_void_p(st.cuda_stream)))
+
+
+def rk_apply_operator_static(n_cells: int, degree: int, Q: int, tau: float, form: int, u: torch.Tensor,
+                             v: torch.Tensor, stream: torch.cuda.Stream | None = None):
+    """v = op(u) without a context or any allocation (the library's static
+    scratch holds the mixed input of RK_OP_CALA / RK_OP_STAGE)."""
+    ns = 1 if form in (RK_OP_K, RK_OP_M) else Q
+    n = ns * (n_cells * degree + 1) ** 3
+    up = _vec(u, n, "u")
+    vp = _vec(v, n, "v", u.dtype)
+    st = stream if stream is not None else torch.cuda.current_stream(u.device)
+    _check(LIB.rk_apply_operator_static(C.byref(rk_mesh(n_cells)), degree, Q, float(tau), int(form),
+                                        _dtype_code(u), up, vp, C.c_void_p(st.cuda_stream)))
 
 
 class DeformedOperator:
