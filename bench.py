@@ -108,7 +108,7 @@ def _counter_rows(path, counter):
 def traffic_record(fetch_csv, write_csv, cz, n=64, k=4, Q=4, reps=3):
     """HBM bytes per launch of the operator kernel with z-chunk length cz:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch, one rocprofv3 --pmc run each,
-    RK_OP_CZ=cz for every launch of the run), averaged over the last `reps`
+    --cz cz for every launch of the run), averaged over the last `reps`
     (timed) operator dispatches, each scaled by the ratio of the known size of
     a plain device copy to what the same counter read for that copy in the
     same run.  Merged into the record of other chunk lengths."""
@@ -125,8 +125,8 @@ def traffic_record(fetch_csv, write_csv, cz, n=64, k=4, Q=4, reps=3):
                 "kernel_source_sha256_16": kernel_hash(), "copy_kernel": COPY_KERNEL, "copy_bytes": copy_bytes,
                 "algorithmic_bytes_per_launch": 8.0 * Q * N ** 3,
                 "commands (per chunk length CZ)": [
-                    f"RK_OP_CZ=CZ rocprofv3 --pmc {c} -d gpurun_out/pmc_{c.split('_')[0].lower()}_czCZ -o op "
-                    f"--output-format csv -- python bench.py --mode op --op-reps {reps}"
+                    f"rocprofv3 --pmc {c} -d gpurun_out/pmc_{c.split('_')[0].lower()}_czCZ -o op "
+                    f"--output-format csv -- python bench.py --mode op --cz CZ --op-reps {reps}"
                     for c in ("FETCH_SIZE", "WRITE_SIZE")]
                 + ["python bench.py --traffic-from gpurun_out/pmc_fetch_czCZ/op_counter_collection.csv "
                    "gpurun_out/pmc_write_czCZ/op_counter_collection.csv --cz CZ"]})
@@ -227,10 +227,63 @@ def cpu_baseline_leg(torch, R, n=16, k=4, Q=4, tau=5e-4, budget_s=12.0):
     cpu = {"value": Q * N ** 3 * reps / t, "unit": "stage-DoFs/s", "cores": 1, "kind": "oracle",
            "sample": f"assembled block operator (lam_i M + tau K, scipy CSR SpMV, single thread) on "
                      f"{n}^3 cells Q_{k} (N={N}), Q={Q}, {reps} applies in {t:.1f} s",
-           "host_cpu_count": os.cpu_count()}
+           "host_cpu_count": os.cpu_count(), "host_cpu_model": host_cpu_model()}
+    cpu.update(oracle_runs())
     acc = accuracy_leg(torch, R, 32, k, Q, tau)
     acc64 = accuracy_leg(torch, R, 64, k, Q, tau)
     return cpu, acc, acc64
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_runs():
+    """Wall time of whole oracle runs on the host (one thread: SuperLU and
+    scipy SpMV are single-threaded):
+    * the 8^3 Q_2 manufactured-solution configuration, Q = 2, tau = 0.05, 10
+      steps by the direct sparse solve of the stage system;
+    * one step of the oracle's FGMRES + block-preconditioned multigrid at
+      8^3 Q_4, Q = 4, tau = 5e-4, rtol 1e-10 (set-up timed apart), and its
+      linear extrapolation in the number of unknowns to 32^3 Q_4 (64 times as
+      many; the iteration count of the multigrid preconditioner does not
+      grow with n), since assembling 32^3 Q_4 on the host takes hours."""
+    import math
+    import numpy as np
+    from oracle.assemble import Problem, interpolate, load_separable
+    from oracle.fgmres import IterativeStepper
+    from oracle.step import DirectStepper
+    from oracle.tableau import RadauIIA
+    t0 = time.perf_counter()
+    n0, k0, Q0, tau0 = 8, 2, 2, 0.05
+    p = Problem(n0, k0)
+    tab = RadauIIA(Q0)
+    G = p.to_int(load_separable(p.mesh, lambda x: np.sin(np.pi * x)))
+    y = p.to_int(interpolate(p.mesh, lambda x, y_, z: np.sin(np.pi * x) * np.sin(np.pi * y_) * np.sin(np.pi * z)))
+    ds = DirectStepper(p.M, p.K, tab, tau0)
+    for st in range(10):
+        gam = np.array([(3 * math.pi ** 2 - 1) * math.exp(-(st + c) * tau0) for c in tab.c])
+        y, _ = ds.step(y, gam[:, None] * G[None, :])
+    t_d0 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    it = IterativeStepper(8, 4, RadauIIA(4), 5e-4)
+    t_setup = time.perf_counter() - t0
+    pp = Problem(8, 4, "kron")
+    yy = np.random.default_rng(0).standard_normal(pp.M.shape[0])
+    t0 = time.perf_counter()
+    _, its, _ = it.step(yy, rtol=1e-10)
+    t_step = time.perf_counter() - t0
+    return {"d0_manufactured_8cubed_q2_10_steps_s": t_d0,
+            "o_iter_8cubed_q4_Q4": {"setup_s": t_setup, "step_s": t_step, "fgmres_iterations": its},
+            "o_iter_32cubed_q4_Q4_step_s_extrapolated": t_step * 64,
+            "threads": 1}
 
 
 def accuracy_leg(torch, R, na, k=4, Qa=4, tau=5e-4):
@@ -266,6 +319,63 @@ def accuracy_leg(torch, R, na, k=4, Qa=4, tau=5e-4):
     del ref, y0
     torch.cuda.empty_cache()
     return acc
+
+
+def time_op_rotated(torch, R, ctx, form, us, vs, reps):
+    """Average launch time of rk_apply_operator cycling through the buffer
+    pairs (us[i], vs[i]) (together larger than the 256 MB Infinity Cache),
+    HIP events on the context's stream."""
+    stream = ctx.stream
+    for u, v in zip(us, vs):
+        R.rk_apply_operator(ctx, form, u, v)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for r in range(reps):
+        R.rk_apply_operator(ctx, form, us[r % len(us)], vs[r % len(vs)])
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) * 1e-3 / reps
+
+
+def fp64_32cubed_legs(torch, R, y0_fn, steps=20, reps=40):
+    """The 32^3 Q_4 fp64 configurations:
+    * the plain per-stage form at Q = 3, tau = 1e-3: `steps` Radau IIA steps
+      from the seeded Fourier data (s per step);
+    * stage-batched at Q = 3 and Q = 5: the operators RK_OP_CALA and
+      RK_OP_BLOCKS in isolation, hot (one buffer pair, which fits in the
+      Infinity Cache) and rotated over buffer pairs of more than 512 MB, in
+      stage-DoFs/s and as a fraction of the HBM roofline (16 B per stage-DoF
+      read + written, fp64); and full steps (s per step)."""
+    n, k, tau = 32, 4, 1e-3
+    N = n * k + 1
+    out = {"grid": f"{n}^3 cells Q_{k} ({N}^3 nodes/stage), tau={tau:g}, fp64, rtol 1e-10"}
+    y0 = y0_fn(n, k)
+    t_ps, its_ps, _ = time_steps(torch, R, n, k, 3, tau, steps, 1, y0, rtol=1e-10,
+                                 precision=R.RK_PREC_FP64, mode=R.RK_PER_STAGE)
+    out["per_stage_Q3"] = {"steps": steps, "ms_per_step": t_ps * 1e3, "fgmres_iterations": its_ps}
+    for Q in (3, 5):
+        sd = Q * N ** 3
+        s = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_FP64, mode=R.RK_BATCHED, rtol=1e-10)
+        nrot = max(2, int(600e6 // (2 * 8 * sd)) + 1)
+        us = [torch.randn(sd, dtype=torch.float64, device="cuda") for _ in range(nrot)]
+        vs = [torch.empty_like(us[0]) for _ in range(nrot)]
+        ops = {}
+        for name, form in (("CALA", R.RK_OP_CALA), ("BLOCKS", R.RK_OP_BLOCKS)):
+            t_hot = time_op(torch, R, s.ctx, form, us[0], vs[0], reps)
+            t_rot = time_op_rotated(torch, R, s.ctx, form, us, vs, reps)
+            ops[name] = {"us_hot": t_hot * 1e6, "us_rotated": t_rot * 1e6,
+                         "stage_dofs_per_s_hot": sd / t_hot, "stage_dofs_per_s_rotated": sd / t_rot,
+                         "hbm_frac_rotated": 16.0 * sd / t_rot / 1e9 / HBM_PEAK_GBS,
+                         "rotated_bytes": 2 * 8 * sd * nrot}
+        s.close()
+        del us, vs
+        torch.cuda.empty_cache()
+        t_b, its_b, _ = time_steps(torch, R, n, k, Q, tau, min(steps, 10), 1, y0, rtol=1e-10,
+                                   precision=R.RK_PREC_FP64, mode=R.RK_BATCHED)
+        out[f"batched_Q{Q}"] = {"operators": ops, "ms_per_step": t_b * 1e3, "fgmres_iterations": its_b}
+    return out
 
 
 BATCH_CELLS = (4, 6, 8, 12, 16, 24, 32, 48)
@@ -399,6 +509,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host leg (oracle)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 per-stage comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven batch of 64 problems")
+    ap.add_argument("--no-fp64-32", action="store_true",
+                    help="skip the 32^3 Q_4 fp64 legs (per-stage Q=3 steps, batched Q=3/5 operators and steps)")
     ap.add_argument("--no-deformed", action="store_true", help="skip the deformed-mesh operator leg")
     ap.add_argument("--no-complex", action="store_true",
                     help="skip the direct complex diagonalisation (PRESB) comparison")
@@ -408,13 +520,15 @@ def main():
     ap.add_argument("--mode", choices=["full", "op", "deformed"], default="full",
                     help="op: only the batched fp32 block operator launches; deformed: only the "
                          "deformed-mesh operator (both for counter runs)")
-    ap.add_argument("--cz", type=int, default=None, help="z-chunk length of the counter runs (--traffic-from)")
+    ap.add_argument("--cz", type=int, default=None,
+                    help="--mode op: fixed z-chunk length (rk_options.z_chunk); --traffic-from: the one the "
+                         "counter runs used")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic record from two rocprofv3 --pmc runs of --mode op")
     args = ap.parse_args()
     if args.traffic_from:
         if args.cz is None:
-            raise SystemExit("--traffic-from needs --cz (the RK_OP_CZ of the counter runs)")
+            raise SystemExit("--traffic-from needs --cz (the z-chunk of the counter runs)")
         rec = traffic_record(*args.traffic_from, cz=args.cz, n=args.n)
         with open(TRAFFIC_FILE, "w") as fh:
             json.dump(rec, fh, indent=1)
@@ -434,7 +548,7 @@ def main():
     if args.mode == "op":
         # explicit Chebyshev bounds: no eigenvalue estimation launches at create
         solver = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, restart=1,
-                            eig_max=[1.0] * R.n_levels(n))
+                            eig_max=[1.0] * R.n_levels(n), z_chunk=args.cz or 0)
         u32 = torch.randn(Q * N ** 3, dtype=torch.float32, device="cuda")
         v32 = torch.empty_like(u32)
         t_blk = time_op(torch, R, solver.ctx, R.RK_OP_BLOCKS, u32, v32, args.op_reps)
@@ -444,7 +558,7 @@ def main():
             v32.copy_(u32)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "op", "kernel": OP_KERNEL, "blocks_fp32_us": t_blk * 1e6,
-                          "level_cz": solver.info["level_cz"][0], "RK_OP_CZ": os.environ.get("RK_OP_CZ"),
+                          "level_cz": solver.info["level_cz"][0], "z_chunk_option": args.cz,
                           "reps": args.op_reps, "GBps": 8.0 * Q * N ** 3 / t_blk / 1e9,
                           "copy_bytes": u32.numel() * 4}), flush=True)
         return 0
@@ -483,7 +597,7 @@ def main():
     torch.cuda.empty_cache()
     sdofs = Q * N ** 3
     # z-chunk of the timed block-operator launches (tuned at create, or forced)
-    cz0 = int(os.environ.get("RK_OP_CZ") or solver.info["level_cz"][0])
+    cz0 = int(solver.info["level_cz"][0])
     x1 = grid_coords(solver.info["nodes"], n)
     y0 = torch.tensor(fourier_field(x1, seed=0), device="cuda")
     opts = solver.opts
@@ -542,6 +656,16 @@ def main():
     y0d = y0
     del y0
     torch.cuda.empty_cache()
+    fp64_32 = None
+    if not args.no_fp64_32:
+        def y0_fn(nn, kk):
+            s_ = R.RadauIIA(nn, kk, 1, 1e-3, autotune=0, restart=1, eig_max=[1.0] * R.n_levels(nn))
+            x = grid_coords(s_.info["nodes"], nn)
+            s_.close()
+            return torch.tensor(fourier_field(x, seed=0), device="cuda")
+        fp64_32 = fp64_32cubed_legs(torch, R, y0_fn)
+        log(f"[bench] 32^3 Q_4 fp64: per-stage Q=3 {fp64_32['per_stage_Q3']['ms_per_step']:.2f} ms/step; batched "
+            f"Q=3 {fp64_32['batched_Q3']['ms_per_step']:.2f}, Q=5 {fp64_32['batched_Q5']['ms_per_step']:.2f} ms/step")
     batch = None
     if not args.no_batch:
         batch = uneven_batch(torch, R)
@@ -588,6 +712,7 @@ def main():
         "deformed_operator": deformed,
         "at_1e-8_accuracy": at_acc,
         "uneven_batch": batch,
+        "fp64_32cubed": fp64_32,
         "step_breakdown_s": {k2: breakdown[k2] for k2 in ("t_rhs", "t_vmult", "t_basis", "t_blocks", "t_rest")},
         "operators": {
             "blocks_fp32_us": t_blk * 1e6,
@@ -596,14 +721,15 @@ def main():
             "cala_fp64_stage_dofs_per_s": sdofs / t_cala,
             "cala_fp64_GBps": 16.0 * sdofs / t_cala / 1e9,
         },
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(cz0),
+        "roofline": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(cz0),
+                     "algorithmic_bytes_per_launch": 8 * sdofs, "bytes_per_stage_dof": 8,
                      "z_chunk": cz0,
                      "kernel": OP_KERNEL + " (batched block operator, all Q stages per launch)",
-                     "flop_per_stage_dof": flop, "algorithmic_flop_per_launch": flop * sdofs,
                      "avg_launch_us": t_blk * 1e6,
-                     "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": hbm_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": 8 * sdofs}},
+                     "alu": {"achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": achieved / ALU_PEAK_TFLOPS, "flop_per_stage_dof": flop,
+                             "algorithmic_flop_per_launch": flop * sdofs}},
     }
     if cpu is not None:
         out["accuracy_vs_oracle"] = acc

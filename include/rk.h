@@ -110,7 +110,12 @@ typedef struct rk_ctx rk_ctx;
 
 /* Uniform mesh of [0,1]^3 with n_cells^3 hexahedra (n_cells = 2^L in Sec. 5;
    any n_cells >= 1 here, with N = n_cells*degree + 1 <= 16384 and N*Q <= 65535).  Multigrid
-   levels halve n_cells while it is even. */
+   levels halve n_cells while it is even, down to the odd part of n_cells
+   (rk_info_t.n_levels, rk_info_t.level_cells).  An odd n_cells therefore has a
+   single level: the "V-cycle" is then the Chebyshev-Jacobi coarse solve on
+   the fine grid alone, with no coarse-grid correction, and the FGMRES
+   iteration count grows with n_cells*degree (tests/test_gpu_step.py pins it
+   for n_cells = 15 against 16).  Use n_cells = m 2^L with a small odd m. */
 typedef struct {
     int32_t n_cells;
 } rk_mesh;
@@ -153,6 +158,11 @@ typedef struct {
                                    Results do not depend on it.  Contexts stepped
                                    concurrently (rk_step_batch) already fill the
                                    GPU; there 1 is faster.                           */
+    int32_t z_chunk;            /* 0: z-chunk of the operator kernel from the
+                                   autotuner (autotune = 1) or a size heuristic;
+                                   1..64: this many elements per z-chunk for every
+                                   operator launch of the context (no tuning).
+                                   Results do not depend on it.                       */
 } rk_options;
 
 typedef struct {
@@ -191,7 +201,7 @@ typedef struct {
 /* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
    max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
    cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0,
-   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1, vc_streams 2. */
+   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1, vc_streams 2, z_chunk 0. */
 void rk_default_options(rk_options* opt);
 
 /* Bytes of device workspace needed for the given mesh, degree (1..6),

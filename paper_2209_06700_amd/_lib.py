@@ -42,7 +42,7 @@ class rk_options(C.Structure):
                 ("eig_safety", C.c_double), ("eig_iterations", C.c_int32),
                 ("eig_max", C.POINTER(C.c_double)), ("timing", C.c_int32), ("method", C.c_int32),
                 ("deform", C.c_double), ("autotune", C.c_int32), ("deform_mg", C.c_int32),
-                ("vc_streams", C.c_int32)]
+                ("vc_streams", C.c_int32), ("z_chunk", C.c_int32)]
 
 
 class rk_stats(C.Structure):

@@ -720,8 +720,7 @@ hipError_t launch_op_typed(const OpLaunch& L) {
     // enough to give every CU several workgroups
     int cz = 16;
     while (cz > 1 && (long long)p.tiles_x * p.tiles_y * ((L.n + cz - 1) / cz) * L.nstage < 2048) cz /= 2;
-    if (L.cz > 0) cz = L.cz;                                                           // tuned per level
-    if (const char* env = std::getenv("RK_OP_CZ")) cz = std::max(1, std::atoi(env));   // tuning override
+    if (L.cz > 0) cz = L.cz;                                                           // tuned or set
     p.cz = cz;
     p.chunks_z = (N + cz * K - 1) / (cz * K);
     p.nwork = p.tiles_x * p.tiles_y * p.chunks_z * L.nstage;

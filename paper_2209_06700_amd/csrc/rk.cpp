@@ -197,6 +197,7 @@ bool valid_options(const rk_options& o, std::string& msg) {
     if (o.autotune != 0 && o.autotune != 1) { msg = "bad autotune flag"; return false; }
     if (o.deform_mg != 0 && o.deform_mg != 1) { msg = "bad deform_mg flag"; return false; }
     if (o.vc_streams < 1 || o.vc_streams > RK_MAX_Q) { msg = "vc_streams out of range"; return false; }
+    if (o.z_chunk < 0 || o.z_chunk > 64) { msg = "z_chunk out of range (0..64)"; return false; }
     if (!(std::fabs(o.deform) <= RK_MAX_DEFORM)) { msg = "|deform| must be <= RK_MAX_DEFORM"; return false; }
     return true;
 }
@@ -362,7 +363,9 @@ int op(rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, vo
     L.stream = c->stream;
     // tuned z-chunk: pair operators of the fine level in fp64, diagonal-mix
     // operators of every level in the preconditioner precision
-    if (cf.pair) {
+    if (c->opt.z_chunk > 0) {
+        L.cz = c->opt.z_chunk;
+    } else if (cf.pair) {
         if (n == c->n && dtype == RK_FP64) L.cz = c->cz_pair;
     } else if (dtype == c->pc) {
         for (const auto& lv : c->lv)
@@ -652,10 +655,9 @@ int blocks_eager(rk_ctx* c) {
 }
 
 // Block solves F.b -> F.x: replay of the captured graph, or eager launches
-// (timing mode, RK_NO_GRAPH set, or capture unavailable).
+// (timing mode, or capture unavailable).
 int run_blocks(rk_ctx* c) {
-    static const bool no_graph = std::getenv("RK_NO_GRAPH") != nullptr;   // A/B override
-    if (c->opt.timing || no_graph || c->vc_graph < 0) return blocks_eager(c);
+    if (c->opt.timing || c->vc_graph < 0) return blocks_eager(c);
     if (c->vc_graph == 0) {
         c->vc_graph = -1;
         if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -979,11 +981,6 @@ int gmres(rk_ctx* c, rk_stats& st, bool& converged) {
                 gg[j] = csg[j] * gg[j];
                 jd[g] = j + 1;
                 if (c->cplx) ++st.block_iterations[g];
-                if (std::getenv("RK_DEBUG_ARNOLDI")) {
-                    std::fprintf(stderr, "[rk] g=%d j=%d |g|/bn=%.3e h:", g, j, std::fabs(gg[j + 1]) / bn[g]);
-                    for (int i = 0; i <= j + 1; ++i) std::fprintf(stderr, " %.6e", hc[i]);
-                    std::fprintf(stderr, "\n");
-                }
                 if (std::fabs(gg[j + 1]) <= c->opt.rtol * bn[g] || hc[j + 1] == 0.0) done[g] = 1;
                 else all = false;
             }
@@ -1063,6 +1060,7 @@ void rk_default_options(rk_options* o) {
     o->autotune = 1;
     o->deform_mg = 1;
     o->vc_streams = 2;
+    o->z_chunk = 0;
 }
 
 int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {
@@ -1177,7 +1175,10 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
     } else if ((rc = estimate_eigs(c))) {
         g_create_error = c->err; delete c; return rc;
     }
-    if (c->opt.autotune && (rc = autotune(c))) {
+    if (c->opt.z_chunk > 0) {   // a fixed chunk for every launch (reported by rk_info)
+        for (auto& lv : c->lv) lv.cz = c->opt.z_chunk;
+        c->cz_pair = c->opt.z_chunk;
+    } else if (c->opt.autotune && (rc = autotune(c))) {
         g_create_error = c->err; delete c; return rc;
     }
     // the private streams and events of split V-cycles, made here rather
@@ -1200,6 +1201,9 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
 
 int rk_destroy(rk_ctx* c) {
     if (!c) return RK_EINVAL;
+    // queued work of the context may still use the workspace the caller
+    // frees after this call
+    (void)hipStreamSynchronize(c->stream);
     for (auto& e : c->event_pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     if (c->vc_exec) (void)hipGraphExecDestroy(c->vc_exec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

@@ -120,8 +120,12 @@ def rk_create(n_cells: int, degree: int, Q: int, tau: float, opts: rk_options | 
         eig_arr = (C.c_double * len(vals))(*vals)
         opts.eig_max = C.cast(eig_arr, C.POINTER(C.c_double))
     nbytes = rk_workspace_bytes(n_cells, degree, Q, opts)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
-    st = stream if stream is not None else torch.cuda.current_stream(ws.device)
+    dev = torch.device(device)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    # The workspace is used on the context stream only: allocate it there, so
+    # that the caching allocator orders its reuse after that stream's work.
+    with torch.cuda.stream(st):
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     mesh = rk_mesh(n_cells)
     h = C.c_void_p()
     rc = LIB.rk_create(C.byref(mesh), degree, Q, float(tau), C.byref(opts), C.c_void_p(ws.data_ptr()),

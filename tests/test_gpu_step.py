@@ -116,6 +116,32 @@ def test_step_vs_modal_oracle(R, n, k, Q, tau, mode, prec):
     solver.close()
 
 
+def test_odd_mesh_has_one_level_and_more_iterations(R):
+    """An odd n_cells has no coarser level: the preconditioner is the
+    Chebyshev-Jacobi solve on the fine grid alone, so FGMRES needs more
+    iterations than on the neighbouring mesh with a multigrid hierarchy, and
+    more still on a finer odd mesh.  The step stays exact to the tolerance."""
+    from oracle.step import ModalSolver
+    from oracle.tableau import RadauIIA
+    from oracle.assemble import Problem
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
+    k, Q, tau = 2, 3, 0.01
+    its = {}
+    for n in (7, 15, 16):
+        print(f"odd mesh n={n}", flush=True)
+        solver = R.RadauIIA(n, k, Q, tau, precision=0, rtol=1e-10)
+        assert solver.info["n_levels"] == R.n_levels(n) == (1 if n % 2 else 5)
+        x1 = grid_coords(solver.info["nodes"], n)
+        y0 = fourier_field(x1, seed=0)
+        p = Problem(n, k, "kron")
+        y = torch.tensor(y0, device="cuda")
+        its[n] = solver.step(0.0, y)["iterations"]
+        y_ref = ModalSolver(n, k).step(RadauIIA(Q), tau, p.to_int(y0))
+        assert _rel(p.to_int(y.cpu().numpy()), y_ref) <= 1e-10
+        solver.close()
+    assert its[15] > its[16] and its[15] > its[7], its
+
+
 def test_noconv_leaves_y_unchanged(R):
     from paper_2209_06700_amd.synthetic import random_vector
     n, k, Q = 4, 2, 3

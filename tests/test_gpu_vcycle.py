@@ -168,30 +168,26 @@ def test_results_do_not_depend_on_the_z_chunk(R):
     autotuner) changes only the work decomposition: V-cycles (every epilogue
     and the transfers), the block operator and the pair operator give
     bitwise equal results for chunks of 1, 2 and 16 elements."""
-    import os
     from paper_2209_06700_amd.synthetic import random_vector
     n, k, Q, tau = 8, 3, 3, 0.02
     N = n * k + 1
     b = random_vector((Q, N ** 3), seed=9, zero_boundary_N=N)
     outs = {}
-    try:
-        for cz in ("1", "2", "16"):
-            os.environ["RK_OP_CZ"] = cz
-            for prec, dt in ((R.RK_PREC_FP64, torch.float64), (R.RK_PREC_MIXED, torch.float32)):
-                ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(precision=prec), eig_max=[2.0, 2.1, 2.2, 2.3])
-                bb = torch.tensor(b, device="cuda", dtype=dt)
-                x = torch.empty_like(bb)
-                R.rk_vcycle(ctx, bb, x)
-                v = torch.empty_like(bb)
-                R.rk_apply_operator(ctx, R.RK_OP_BLOCKS, bb, v)
-                b64 = bb.double()
-                w = torch.empty_like(b64)
-                R.rk_apply_operator(ctx, R.RK_OP_CALA, b64, w)
-                torch.cuda.synchronize()
-                outs[(cz, prec)] = (x.cpu(), v.cpu(), w.cpu())
-                R.rk_destroy(ctx)
-    finally:
-        os.environ.pop("RK_OP_CZ", None)
+    for cz in ("1", "2", "16"):
+        for prec, dt in ((R.RK_PREC_FP64, torch.float64), (R.RK_PREC_MIXED, torch.float32)):
+            ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(precision=prec, z_chunk=int(cz)),
+                              eig_max=[2.0, 2.1, 2.2, 2.3])
+            bb = torch.tensor(b, device="cuda", dtype=dt)
+            x = torch.empty_like(bb)
+            R.rk_vcycle(ctx, bb, x)
+            v = torch.empty_like(bb)
+            R.rk_apply_operator(ctx, R.RK_OP_BLOCKS, bb, v)
+            b64 = bb.double()
+            w = torch.empty_like(b64)
+            R.rk_apply_operator(ctx, R.RK_OP_CALA, b64, w)
+            torch.cuda.synchronize()
+            outs[(cz, prec)] = (x.cpu(), v.cpu(), w.cpu())
+            R.rk_destroy(ctx)
     for prec in (R.RK_PREC_FP64, R.RK_PREC_MIXED):
         for cz in ("2", "16"):
             for a, c in zip(outs[("1", prec)], outs[(cz, prec)]):
