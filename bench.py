@@ -80,10 +80,14 @@ def kernel_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(cz):
+def traffic_key(cz, ts=0):
+    return str(cz) if ts == 0 else f"ts{ts}_cz{cz}"
+
+
+def measured_traffic(cz, ts=0):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source with the z-chunk length `cz` that
-    the timed launches use."""
+    was taken on the current kernel source with the z-chunk length `cz` and
+    tile shape `ts` that the timed launches use."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -91,7 +95,7 @@ def measured_traffic(cz):
         return None
     if rec.get("kernel_source_sha256_16") != kernel_hash():
         return None
-    return rec.get("by_cz", {}).get(str(cz), {}).get("hbm_bytes_per_launch")
+    return rec.get("by_cz", {}).get(traffic_key(cz, ts), {}).get("hbm_bytes_per_launch")
 
 
 def _counter_rows(path, counter):
@@ -105,7 +109,7 @@ def _counter_rows(path, counter):
     return out
 
 
-def traffic_record(fetch_csv, write_csv, cz, n=64, k=4, Q=4, reps=3):
+def traffic_record(fetch_csv, write_csv, cz, n=64, k=4, Q=4, reps=3, ts=0):
     """HBM bytes per launch of the operator kernel with z-chunk length cz:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch, one rocprofv3 --pmc run each,
     --cz cz for every launch of the run), averaged over the last `reps`
@@ -126,10 +130,10 @@ def traffic_record(fetch_csv, write_csv, cz, n=64, k=4, Q=4, reps=3):
                 "algorithmic_bytes_per_launch": 8.0 * Q * N ** 3,
                 "commands (per chunk length CZ)": [
                     f"rocprofv3 --pmc {c} -d gpurun_out/pmc_{c.split('_')[0].lower()}_czCZ -o op "
-                    f"--output-format csv -- python bench.py --mode op --cz CZ --op-reps {reps}"
+                    f"--output-format csv -- python bench.py --mode op --cz CZ --tile-shape TS --op-reps {reps}"
                     for c in ("FETCH_SIZE", "WRITE_SIZE")]
                 + ["python bench.py --traffic-from gpurun_out/pmc_fetch_czCZ/op_counter_collection.csv "
-                   "gpurun_out/pmc_write_czCZ/op_counter_collection.csv --cz CZ"]})
+                   "gpurun_out/pmc_write_czCZ/op_counter_collection.csv --cz CZ --tile-shape TS"]})
     rec.pop("commands", None)
     entry = {}
     total = 0.0
@@ -148,7 +152,7 @@ def traffic_record(fetch_csv, write_csv, cz, n=64, k=4, Q=4, reps=3):
         total += kib_op * 1024.0 * scale
     entry["hbm_bytes_per_launch"] = total
     entry["bytes_per_stage_dof"] = total / (Q * N ** 3)
-    rec.setdefault("by_cz", {})[str(cz)] = entry
+    rec.setdefault("by_cz", {})[traffic_key(cz, ts)] = entry
     return rec
 
 
@@ -523,13 +527,16 @@ def main():
     ap.add_argument("--cz", type=int, default=None,
                     help="--mode op: fixed z-chunk length (rk_options.z_chunk); --traffic-from: the one the "
                          "counter runs used")
+    ap.add_argument("--tile-shape", type=int, default=0,
+                    help="with --cz: the tile shape (rk_options.tile_shape) of the op-mode launches and of the "
+                         "counter runs (--traffic-from)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic record from two rocprofv3 --pmc runs of --mode op")
     args = ap.parse_args()
     if args.traffic_from:
         if args.cz is None:
             raise SystemExit("--traffic-from needs --cz (the z-chunk of the counter runs)")
-        rec = traffic_record(*args.traffic_from, cz=args.cz, n=args.n)
+        rec = traffic_record(*args.traffic_from, cz=args.cz, n=args.n, ts=args.tile_shape)
         with open(TRAFFIC_FILE, "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))
@@ -548,7 +555,8 @@ def main():
     if args.mode == "op":
         # explicit Chebyshev bounds: no eigenvalue estimation launches at create
         solver = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, restart=1,
-                            eig_max=[1.0] * R.n_levels(n), z_chunk=args.cz or 0)
+                            eig_max=[1.0] * R.n_levels(n), z_chunk=args.cz or 0,
+                            tile_shape=args.tile_shape if args.cz else 0)
         u32 = torch.randn(Q * N ** 3, dtype=torch.float32, device="cuda")
         v32 = torch.empty_like(u32)
         t_blk = time_op(torch, R, solver.ctx, R.RK_OP_BLOCKS, u32, v32, args.op_reps)
@@ -558,7 +566,8 @@ def main():
             v32.copy_(u32)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "op", "kernel": OP_KERNEL, "blocks_fp32_us": t_blk * 1e6,
-                          "level_cz": solver.info["level_cz"][0], "z_chunk_option": args.cz,
+                          "level_cz_store": solver.info["level_cz_store"][0],
+                          "level_ts_store": solver.info["level_ts_store"][0], "z_chunk_option": args.cz,
                           "reps": args.op_reps, "GBps": 8.0 * Q * N ** 3 / t_blk / 1e9,
                           "copy_bytes": u32.numel() * 4}), flush=True)
         return 0
@@ -597,7 +606,8 @@ def main():
     torch.cuda.empty_cache()
     sdofs = Q * N ** 3
     # z-chunk of the timed block-operator launches (tuned at create, or forced)
-    cz0 = int(solver.info["level_cz"][0])
+    cz0 = int(solver.info["level_cz_store"][0])
+    ts0 = int(solver.info["level_ts_store"][0])
     x1 = grid_coords(solver.info["nodes"], n)
     y0 = torch.tensor(fourier_field(x1, seed=0), device="cuda")
     opts = solver.opts
@@ -722,9 +732,9 @@ def main():
             "cala_fp64_GBps": 16.0 * sdofs / t_cala / 1e9,
         },
         "roofline": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(cz0),
+                     "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(cz0, ts0),
                      "algorithmic_bytes_per_launch": 8 * sdofs, "bytes_per_stage_dof": 8,
-                     "z_chunk": cz0,
+                     "z_chunk": cz0, "tile_shape": ts0,
                      "kernel": OP_KERNEL + " (batched block operator, all Q stages per launch)",
                      "avg_launch_us": t_blk * 1e6,
                      "alu": {"achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",

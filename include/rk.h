@@ -140,9 +140,12 @@ typedef struct {
                                    (|eps| <= RK_MAX_DEFORM, see rk_deformed_apply);
                                    the V-cycles as selected by deform_mg             */
     int32_t autotune;           /* 1: at create, time the operator kernel's z-chunk
-                                   length (1, 2, 4, 8, 16 elements) on every level and
-                                   for the fp64 Krylov operator, and keep the fastest;
-                                   0: a size heuristic                               */
+                                   length (1, 2, 4, 8, 16 elements) and, for an fp32
+                                   preconditioner, its x-y tile shape (about 32 or 64
+                                   x-nodes) on every level, separately for the V-cycle
+                                   epilogues and the plain operator, and the z-chunk
+                                   of the fp64 Krylov operator; keep the fastest.
+                                   0: a size heuristic, the narrow tiles             */
     int32_t deform_mg;          /* deform != 0 only.  1: V-cycles on the deformed
                                    levels (each level rediscretised on its mapped mesh,
                                    stored Jacobi diagonals, Chebyshev updates as
@@ -163,6 +166,9 @@ typedef struct {
                                    1..64: this many elements per z-chunk for every
                                    operator launch of the context (no tuning).
                                    Results do not depend on it.                       */
+    int32_t tile_shape;         /* with z_chunk > 0: the x-y tile shape of the fp32
+                                   diagonal-mix kernels, 0 (about 32 x-nodes) or 1
+                                   (about 64).  Results do not depend on it.           */
 } rk_options;
 
 typedef struct {
@@ -194,14 +200,21 @@ typedef struct {
     double  clam_re[RK_MAX_Q], clam_im[RK_MAX_Q];   /* lam of block j (Im >= 0)     */
     double  T[RK_MAX_Q * RK_MAX_Q], U[RK_MAX_Q * RK_MAX_Q];   /* row-major, T = U^-1 */
     int32_t level_cz[RK_MAX_LEVELS];      /* z-chunk of the level's block operator
-                                             (0: size heuristic), autotune = 1   */
+                                             in the V-cycle epilogues (smoother,
+                                             residual; 0: size heuristic)         */
     int32_t krylov_cz;                    /* same for the fp64 Krylov operator     */
+    int32_t level_ts[RK_MAX_LEVELS];      /* tile shape of the V-cycle epilogues:
+                                             0 about 32 x-nodes, 1 about 64 (fp32
+                                             preconditioner only)                 */
+    int32_t level_cz_store[RK_MAX_LEVELS];/* z-chunk and tile shape of the level's */
+    int32_t level_ts_store[RK_MAX_LEVELS];/* plain block operator (RK_OP_BLOCKS)   */
 } rk_info_t;
 
 /* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
    max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
    cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0,
-   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1, vc_streams 2, z_chunk 0. */
+   RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1, vc_streams 2, z_chunk 0,
+   tile_shape 0. */
 void rk_default_options(rk_options* opt);
 
 /* Bytes of device workspace needed for the given mesh, degree (1..6),

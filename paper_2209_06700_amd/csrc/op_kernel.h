@@ -82,9 +82,12 @@ struct DG {
     static constexpr double v = R == 0 ? EC<K, W, 0, 0>::v + EC<K, W, K, K>::v : EC<K, W, R, R>::v;
 };
 
-template <int K>
+// Tile shapes (TS): 0 = about 32 x-nodes, 1 = about 64 x-nodes (fp32
+// diagonal-mix kernels only), both 8 pencils tall.  The autotuner picks one
+// per level and epilogue class.
+template <int K, int TS = 0>
 struct Tile {
-    static constexpr int CX = (32 / K) > 0 ? (32 / K) : 1;  // elements per tile in x
+    static constexpr int CX = ((TS == 1 ? 64 : 32) / K) > 0 ? ((TS == 1 ? 64 : 32) / K) : 1;  // elements in x
     static constexpr int TX = CX * K;                       // owned nodes in x
     // pencils per tile in y (taller tiles cut the x-pass halo rows but leave
     // fewer resident workgroups per CU, which measured slower)
@@ -163,9 +166,9 @@ struct MinWaves {
     static constexpr int v = (sizeof(T) == 4 && K <= 4 && (EPI == EPI_CHEB || EPI == EPI_CHEB1)) ? 4 : 1;
 };
 
-template <int K, typename T, int MIX, int EPI>
-__global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kernel(OpArgs<T> p) {
-    using TL = Tile<K>;
+template <int K, typename T, int MIX, int EPI, int TS>
+__global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) op_kernel(OpArgs<T> p) {
+    using TL = Tile<K, TS>;
     constexpr int P = K + 1;
     constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, RX = TL::RX, RY = TL::RY;
     constexpr int XP = TL::XP, CX = TL::CX;
@@ -700,9 +703,9 @@ __global__ void __launch_bounds__(Tile<K>::NT, (MinWaves<K, T, EPI>::v)) op_kern
     }
 }
 
-template <int K, typename T>
-hipError_t launch_op_typed(const OpLaunch& L) {
-    using TL = Tile<K>;
+template <int K, typename T, int TS>
+hipError_t launch_op_shape(const OpLaunch& L) {
+    using TL = Tile<K, TS>;
     OpArgs<T> p;
     p.u = static_cast<const T*>(L.u);
     p.u2 = static_cast<const T*>(L.u2);
@@ -738,17 +741,28 @@ hipError_t launch_op_typed(const OpLaunch& L) {
     dim3 grid(8 * p.per_xcd), block(TL::NT);
 #define RK_OP_CASE(MX, EP)                                                      \
     if (L.mix == MX && L.epi == EP) {                                           \
-        op_kernel<K, T, MX, EP><<<grid, block, 0, L.stream>>>(p);               \
+        op_kernel<K, T, MX, EP, TS><<<grid, block, 0, L.stream>>>(p);           \
         return hipGetLastError();                                               \
     }
     RK_OP_CASE(MIX_DIAG, EPI_STORE)
     RK_OP_CASE(MIX_DIAG, EPI_RESID)
     RK_OP_CASE(MIX_DIAG, EPI_CHEB)
     RK_OP_CASE(MIX_DIAG, EPI_CHEB1)
-    RK_OP_CASE(MIX_PAIR, EPI_STORE)
-    RK_OP_CASE(MIX_PAIR, EPI_RESID)
+    if constexpr (TS == 0) {
+        RK_OP_CASE(MIX_PAIR, EPI_STORE)
+        RK_OP_CASE(MIX_PAIR, EPI_RESID)
+    }
 #undef RK_OP_CASE
     return hipErrorInvalidValue;
+}
+
+template <int K, typename T>
+hipError_t launch_op_typed(const OpLaunch& L) {
+    if constexpr (sizeof(T) == 4) {
+        if (L.ts == 1 && L.mix == MIX_DIAG) return launch_op_shape<K, T, 1>(L);
+    }
+    if (L.ts != 0 && L.ts != 1) return hipErrorInvalidValue;
+    return launch_op_shape<K, T, 0>(L);
 }
 
 template <int K>

@@ -74,7 +74,10 @@ struct Level {
     void* y = nullptr;
     Coeffs blk;             // block operators lam_i M + tau K on this level
     double eig_max = 1.0;
-    int cz = 0;             // tuned z-chunk of the diagonal-mix operator (0: heuristic)
+    int cz = 0;             // tuned z-chunk of the diagonal-mix operator (0: heuristic),
+    int ts = 0;             // and its tile shape, for the V-cycle epilogues
+    int cz_st = 0;          // the same for the plain (store) epilogue
+    int ts_st = 0;
     // multigrid on the deformed mesh: per-point geometry, Jacobi diagonals of
     // M and K, and an operator output temp ([Q][N3]), preconditioner dtype
     void* geo = nullptr;
@@ -198,6 +201,7 @@ bool valid_options(const rk_options& o, std::string& msg) {
     if (o.deform_mg != 0 && o.deform_mg != 1) { msg = "bad deform_mg flag"; return false; }
     if (o.vc_streams < 1 || o.vc_streams > RK_MAX_Q) { msg = "vc_streams out of range"; return false; }
     if (o.z_chunk < 0 || o.z_chunk > 64) { msg = "z_chunk out of range (0..64)"; return false; }
+    if (o.tile_shape != 0 && o.tile_shape != 1) { msg = "tile_shape must be 0 or 1"; return false; }
     if (!(std::fabs(o.deform) <= RK_MAX_DEFORM)) { msg = "|deform| must be <= RK_MAX_DEFORM"; return false; }
     return true;
 }
@@ -369,7 +373,10 @@ int op(rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, vo
         if (n == c->n && dtype == RK_FP64) L.cz = c->cz_pair;
     } else if (dtype == c->pc) {
         for (const auto& lv : c->lv)
-            if (lv.n == n) L.cz = lv.cz;
+            if (lv.n == n) {
+                L.cz = epi == EPI_STORE ? lv.cz_st : lv.cz;
+                L.ts = epi == EPI_STORE ? lv.ts_st : lv.ts;
+            }
     }
     HIPCHK(c, launch_op(L));
     return RK_OK;
@@ -773,35 +780,51 @@ int time_launches(rk_ctx* c, int reps, F&& fn, float* ms) {
 // single lucky round does not).  The operator's results do not depend on the
 // choice (the work decomposition changes, the arithmetic of every output
 // does not).
-int pick_chunk(rk_ctx* c, int* cz_slot, const std::function<int()>& launch) {
+// Times the launches with every z-chunk of 1..16 elements and, if ts_slot is
+// given, both tile shapes: three interleaved rounds of four launches each
+// after a warm-up; the lowest mean wins.
+int pick_chunk(rk_ctx* c, int* cz_slot, const std::function<int()>& launch, int* ts_slot = nullptr) {
     static const int cand[] = {1, 2, 4, 8, 16};
-    constexpr int nc = 5, rounds = 3;
-    float sum[nc] = {};
+    constexpr int ncz = 5, rounds = 3;
+    const int nts = ts_slot ? 2 : 1;
+    float sum[2 * ncz] = {};
     *cz_slot = 0;                                    // warm-up with the size heuristic
+    if (ts_slot) *ts_slot = 0;
     for (int i = 0; i < 8; ++i)
         if (int rc = launch()) return rc;
     for (int r = 0; r < rounds; ++r)
-        for (int i = 0; i < nc; ++i) {
-            *cz_slot = cand[i];
-            float ms = 0.f;
-            if (int rc = time_launches(c, 4, launch, &ms)) return rc;
-            sum[i] += ms;
-        }
+        for (int t = 0; t < nts; ++t)
+            for (int i = 0; i < ncz; ++i) {
+                *cz_slot = cand[i];
+                if (ts_slot) *ts_slot = t;
+                float ms = 0.f;
+                if (int rc = time_launches(c, 4, launch, &ms)) return rc;
+                sum[t * ncz + i] += ms;
+            }
     int pick = 0;
-    for (int i = 1; i < nc; ++i)
+    for (int i = 1; i < nts * ncz; ++i)
         if (sum[i] < sum[pick]) pick = i;
-    *cz_slot = cand[pick];
+    *cz_slot = cand[pick % ncz];
+    if (ts_slot) *ts_slot = pick / ncz;
     return RK_OK;
 }
 
 int autotune(rk_ctx* c) {
     const int ns = c->opt.mode == RK_BATCHED ? c->Q : 1;
+    // the second tile shape exists for the fp32 diagonal-mix kernels only
+    const bool shapes = c->pc == RK_FP32;
     for (size_t l = 0; l < c->lv.size() && !c->dmg; ++l) {
         Level& L = c->lv[l];
         HIPCHK(c, launch_random_fill(c->pc, L.x, L.N, c->Q, 777u + (unsigned)l, c->stream));
+        HIPCHK(c, launch_random_fill(c->pc, L.b, L.N, c->Q, 999u + (unsigned)l, c->stream));
+        // the V-cycle epilogues, timed as the Chebyshev update (the most frequent)
         int rc = pick_chunk(c, &L.cz, [&] {
+            return op(c, c->k, c->pc, EPI_CHEB, L.blk, L.x, L.y, L.b, nullptr, L.n, 0, ns, 0.5, 0.5);
+        }, shapes ? &L.ts : nullptr);
+        if (rc) return rc;
+        rc = pick_chunk(c, &L.cz_st, [&] {
             return op(c, c->k, c->pc, EPI_STORE, L.blk, L.x, L.y, nullptr, nullptr, L.n, 0, ns, 0, 0);
-        });
+        }, shapes ? &L.ts_st : nullptr);
         if (rc) return rc;
     }
     // fine-level fp64 pair operator (mass input in mbuf, stiffness input in w)
@@ -1061,6 +1084,7 @@ void rk_default_options(rk_options* o) {
     o->deform_mg = 1;
     o->vc_streams = 2;
     o->z_chunk = 0;
+    o->tile_shape = 0;
 }
 
 int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {
@@ -1176,7 +1200,10 @@ int rk_create(const rk_mesh* mesh, int degree, int Q, double tau, const rk_optio
         g_create_error = c->err; delete c; return rc;
     }
     if (c->opt.z_chunk > 0) {   // a fixed chunk for every launch (reported by rk_info)
-        for (auto& lv : c->lv) lv.cz = c->opt.z_chunk;
+        for (auto& lv : c->lv) {
+            lv.cz = lv.cz_st = c->opt.z_chunk;
+            lv.ts = lv.ts_st = c->pc == RK_FP32 ? c->opt.tile_shape : 0;
+        }
         c->cz_pair = c->opt.z_chunk;
     } else if (c->opt.autotune && (rc = autotune(c))) {
         g_create_error = c->err; delete c; return rc;
@@ -1233,7 +1260,12 @@ int rk_info(const rk_ctx* c, rk_info_t* o) {
     o->n_pairs = c->tab.npair;
     for (int i = 0; i < Q; ++i) { o->clam_re[i] = c->tab.clam_re[i]; o->clam_im[i] = c->tab.clam_im[i]; }
     for (int i = 0; i < Q * Q; ++i) { o->T[i] = c->tab.CT[i]; o->U[i] = c->tab.CU[i]; }
-    for (size_t l = 0; l < c->lv.size(); ++l) o->level_cz[l] = c->lv[l].cz;
+    for (size_t l = 0; l < c->lv.size(); ++l) {
+        o->level_cz[l] = c->lv[l].cz;
+        o->level_ts[l] = c->lv[l].ts;
+        o->level_cz_store[l] = c->lv[l].cz_st;
+        o->level_ts_store[l] = c->lv[l].ts_st;
+    }
     o->krylov_cz = c->cz_pair;
     return RK_OK;
 }

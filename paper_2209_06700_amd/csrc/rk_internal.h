@@ -107,6 +107,7 @@ struct OpLaunch {
     int xo_from_b = 0;
     double c0 = 0.0;
     int cz = 0;                // elements per z-chunk of a work item (0: size heuristic)
+    int ts = 0;                // tile shape: 0 (about 32 x-nodes) or 1 (about 64; fp32 diagonal mix)
     hipStream_t stream = nullptr;
 };
 hipError_t launch_op(const OpLaunch& L);

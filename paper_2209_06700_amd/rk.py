@@ -153,7 +153,9 @@ def rk_info(ctx: Context) -> dict:
                 eig_max=list(i.eig_max[:nl]), nodes=list(i.nodes[:i.degree + 1]),
                 n_blocks=i.n_blocks, n_pairs=i.n_pairs,
                 clam=[complex(i.clam_re[j], i.clam_im[j]) for j in range(i.n_blocks)],
-                T=mat(i.T), U=mat(i.U), level_cz=list(i.level_cz[:nl]), krylov_cz=i.krylov_cz)
+                T=mat(i.T), U=mat(i.U), level_cz=list(i.level_cz[:nl]), krylov_cz=i.krylov_cz,
+                level_ts=list(i.level_ts[:nl]), level_cz_store=list(i.level_cz_store[:nl]),
+                level_ts_store=list(i.level_ts_store[:nl]))
 
 
 def rk_step(ctx: Context, t_n: float, y: torch.Tensor, G: torch.Tensor | None = None,

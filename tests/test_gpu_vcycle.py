@@ -163,20 +163,24 @@ def test_setup_tableau_matches_oracle(R, Q):
         assert np.abs(got - want).max() <= tol * scale, (key, np.abs(got - want).max())
 
 
-def test_results_do_not_depend_on_the_z_chunk(R):
-    """The operator kernel's z-chunk length (tuned per level by the
-    autotuner) changes only the work decomposition: V-cycles (every epilogue
-    and the transfers), the block operator and the pair operator give
-    bitwise equal results for chunks of 1, 2 and 16 elements."""
+@pytest.mark.parametrize("n", [8, 24])
+def test_results_do_not_depend_on_the_z_chunk(R, n):
+    """The operator kernel's z-chunk length and x-y tile shape (tuned per
+    level by the autotuner) change only the work decomposition: V-cycles
+    (every epilogue and the transfers), the block operator and the pair
+    operator give bitwise equal results for chunks of 1, 2 and 16 elements,
+    and (fp32 preconditioner) for both tile shapes."""
     from paper_2209_06700_amd.synthetic import random_vector
-    n, k, Q, tau = 8, 3, 3, 0.02
+    k, Q, tau = 3, 3, 0.02
     N = n * k + 1
     b = random_vector((Q, N ** 3), seed=9, zero_boundary_N=N)
     outs = {}
-    for cz in ("1", "2", "16"):
+    for cz in ("1", "2", "16", "2t", "16t"):
         for prec, dt in ((R.RK_PREC_FP64, torch.float64), (R.RK_PREC_MIXED, torch.float32)):
-            ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(precision=prec, z_chunk=int(cz)),
-                              eig_max=[2.0, 2.1, 2.2, 2.3])
+            ts = 1 if cz.endswith("t") else 0
+            ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(precision=prec, z_chunk=int(cz.rstrip("t")),
+                                                                 tile_shape=ts),
+                              eig_max=[2.0, 2.1, 2.2, 2.3][:R.n_levels(n)])
             bb = torch.tensor(b, device="cuda", dtype=dt)
             x = torch.empty_like(bb)
             R.rk_vcycle(ctx, bb, x)
@@ -189,7 +193,7 @@ def test_results_do_not_depend_on_the_z_chunk(R):
             outs[(cz, prec)] = (x.cpu(), v.cpu(), w.cpu())
             R.rk_destroy(ctx)
     for prec in (R.RK_PREC_FP64, R.RK_PREC_MIXED):
-        for cz in ("2", "16"):
+        for cz in ("2", "16", "2t", "16t"):
             for a, c in zip(outs[("1", prec)], outs[(cz, prec)]):
                 assert torch.equal(a, c), (cz, prec)
 
