@@ -169,6 +169,12 @@ typedef struct {
     int32_t tile_shape;         /* with z_chunk > 0: the x-y tile shape of the fp32
                                    diagonal-mix kernels, 0 (about 32 x-nodes) or 1
                                    (about 64).  Results do not depend on it.           */
+    int32_t tail_nodes;         /* affine-mesh V-cycles: the levels of at most this
+                                   many nodes per stage (N^3), down to the coarsest,
+                                   run in one launch with one workgroup per stage
+                                   block (rk_info_t.tail_level); 0: every level
+                                   launches its own kernels.  Results agree with the
+                                   multi-launch V-cycle up to rounding.              */
 } rk_options;
 
 typedef struct {
@@ -208,13 +214,15 @@ typedef struct {
                                              preconditioner only)                 */
     int32_t level_cz_store[RK_MAX_LEVELS];/* z-chunk and tile shape of the level's */
     int32_t level_ts_store[RK_MAX_LEVELS];/* plain block operator (RK_OP_BLOCKS)   */
+    int32_t tail_level;                   /* first level of the one-launch coarse
+                                             end of the V-cycle (-1: none)        */
 } rk_info_t;
 
 /* Fills *opt with the defaults: RK_PREC_FP64, RK_BATCHED, rtol 1e-10,
    max_iter 200, restart 30, cheb_degree 3, coarse_cheb_degree 3,
    cheb_range 15, eig_safety 1.2, eig_iterations 30, eig_max NULL, timing 0,
    RK_METHOD_CROUT, deform 0, autotune 1, deform_mg 1, vc_streams 2, z_chunk 0,
-   tile_shape 0. */
+   tile_shape 0, tail_nodes 4913 (17^3). */
 void rk_default_options(rk_options* opt);
 
 /* Bytes of device workspace needed for the given mesh, degree (1..6),

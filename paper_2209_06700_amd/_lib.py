@@ -42,7 +42,8 @@ class rk_options(C.Structure):
                 ("eig_safety", C.c_double), ("eig_iterations", C.c_int32),
                 ("eig_max", C.POINTER(C.c_double)), ("timing", C.c_int32), ("method", C.c_int32),
                 ("deform", C.c_double), ("autotune", C.c_int32), ("deform_mg", C.c_int32),
-                ("vc_streams", C.c_int32), ("z_chunk", C.c_int32), ("tile_shape", C.c_int32)]
+                ("vc_streams", C.c_int32), ("z_chunk", C.c_int32), ("tile_shape", C.c_int32),
+                ("tail_nodes", C.c_int32)]
 
 
 class rk_stats(C.Structure):
@@ -65,7 +66,7 @@ class rk_info_t(C.Structure):
                 ("T", C.c_double * 81), ("U", C.c_double * 81),
                 ("level_cz", C.c_int32 * RK_MAX_LEVELS), ("krylov_cz", C.c_int32),
                 ("level_ts", C.c_int32 * RK_MAX_LEVELS), ("level_cz_store", C.c_int32 * RK_MAX_LEVELS),
-                ("level_ts_store", C.c_int32 * RK_MAX_LEVELS)]
+                ("level_ts_store", C.c_int32 * RK_MAX_LEVELS), ("tail_level", C.c_int32)]
 
 
 def load():

@@ -19,7 +19,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librk.so")
 
 ARCH = "gfx950"
-SOURCES = ["host_math.cpp", "rk.cpp", "kernels_misc.hip", "transfer_kernels.hip", "deformed_kernels.hip", "noalloc.hip"] + [f"ops_k{k}.hip" for k in range(1, 7)]
+SOURCES = ["host_math.cpp", "rk.cpp", "kernels_misc.hip", "transfer_kernels.hip", "deformed_kernels.hip", "noalloc.hip", "tail_kernels.hip"] + [f"ops_k{k}.hip" for k in range(1, 7)]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -144,6 +144,11 @@ struct rk_ctx {
     Coeffs form[F_NFORMS];         // fine-level operator coefficients
     Coeffs presb_m;                // PRESB coupling: Im(lam_j) M on slots nb + j
     int cz_pair = 0;               // tuned z-chunk of the fine-level fp64 pair operator
+    // The coarse end of the V-cycle from level tail_level down runs in one
+    // launch (-1: none); its per-stage scratch holds 4 N^3 of that level.
+    int tail_level = -1;
+    void* tail = nullptr;
+    size_t tail_stage = 0;
     void* tmp = nullptr;           // restriction intermediate, [Q][tmp_stage]
     size_t tmp_stage = 0;          // its per-stage size: the largest N_l N_(l+1)^2
     long long ld = 0;              // stride of the Krylov vectors (Q N3 padded to 256 bytes)
@@ -202,6 +207,7 @@ bool valid_options(const rk_options& o, std::string& msg) {
     if (o.vc_streams < 1 || o.vc_streams > RK_MAX_Q) { msg = "vc_streams out of range"; return false; }
     if (o.z_chunk < 0 || o.z_chunk > 64) { msg = "z_chunk out of range (0..64)"; return false; }
     if (o.tile_shape != 0 && o.tile_shape != 1) { msg = "tile_shape must be 0 or 1"; return false; }
+    if (o.tail_nodes < 0) { msg = "tail_nodes must be >= 0"; return false; }
     if (!(std::fabs(o.deform) <= RK_MAX_DEFORM)) { msg = "|deform| must be <= RK_MAX_DEFORM"; return false; }
     return true;
 }
@@ -264,6 +270,10 @@ size_t carve(rk_ctx& c, char* base) {
         tmp = std::max(tmp, (size_t)c.lv[l].N * c.lv[l + 1].N * c.lv[l + 1].N);
     c.tmp_stage = tmp;
     c.tmp = cv.take(pcs * Q * tmp);
+    if (c.tail_level >= 0) {
+        c.tail_stage = 4 * (size_t)c.lv[c.tail_level].N3;
+        c.tail = cv.take(pcs * Q * c.tail_stage);
+    }
     const long long qn = (long long)Q * c.N3;
     const int m = c.opt.restart;
     // Krylov vectors are qn long, stored at a stride padded to 256 bytes
@@ -319,6 +329,15 @@ int setup_sizes(rk_ctx& c, const rk_mesh* mesh, int degree, int Q, const rk_opti
         L.h = 1.0 / m;
         c.lv.push_back(L);
     }
+    // the one-launch coarse end: affine-mesh levels of at most tail_nodes
+    // nodes, if the tail kernel can take all of them
+    c.tail_level = -1;
+    if (!c.dmg && c.opt.tail_nodes > 0)
+        for (size_t l = 0; l < c.lv.size(); ++l)
+            if (c.lv[l].N3 <= c.opt.tail_nodes) {
+                if ((int)(c.lv.size() - l) <= kTailMaxLevels) c.tail_level = (int)l;
+                break;
+            }
     return RK_OK;
 }
 
@@ -543,8 +562,41 @@ int prolong_add(rk_ctx* c, int l, int s0, int ns, const void* coarse, void* fine
 // One V-cycle on level l for stages [s0, s0+ns): b -> result, using the two
 // buffers first/second.  For l < last the result always lands in `second`;
 // on the coarsest level in `first` for an odd coarse degree, else `second`.
+// The V-cycle from level l (>= tail_level) down to the coarsest and back in
+// one launch, one workgroup per stage block; the result lands in the buffer
+// the multi-launch path would use.
+int tail_vcycle(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, void* second, void** res) {
+    const int last = (int)c->lv.size() - 1;
+    TailArgs a;
+    a.nlev = last - l + 1;
+    a.s0 = s0;
+    a.dtype = c->pc;
+    a.scratch = c->tail;
+    a.sstride = (long long)c->tail_stage;
+    a.n3max = c->lv[c->tail_level].N3;
+    for (int i = 0; i < a.nlev; ++i) {
+        const Level& L = c->lv[l + i];
+        TailLevel& t = a.lv[i];
+        t.b = i == 0 ? const_cast<void*>(b) : L.b;
+        t.x = i == 0 ? first : L.x;
+        t.y = i == 0 ? second : L.y;
+        t.N3 = L.N3;
+        t.n = L.n;
+        t.degree = l + i == last ? c->opt.coarse_cheb_degree : c->opt.cheb_degree;
+        const ChebCoef cc = cheb_coef(L.eig_max, c->opt.cheb_range);
+        t.theta = cc.theta;
+        t.delta = cc.delta;
+        t.sigma = cc.sigma;
+        for (int q = 0; q < RK_MAX_Q; ++q) { t.alpha[q] = L.blk.alpha[q]; t.beta[q] = L.blk.beta[q]; }
+    }
+    HIPCHK(c, launch_tail_vcycle(c->k, a, ns, c->stream));
+    *res = (a.nlev > 1 || c->opt.coarse_cheb_degree % 2 == 0) ? second : first;
+    return RK_OK;
+}
+
 int vcycle_level(rk_ctx* c, int l, int s0, int ns, const void* b, void* first, void* second, void** res) {
     const int last = (int)c->lv.size() - 1;
+    if (c->tail_level >= 0 && l >= c->tail_level) return tail_vcycle(c, l, s0, ns, b, first, second, res);
     if (l == last) return chebyshev(c, l, s0, ns, b, first, second, true, c->opt.coarse_cheb_degree, res);
     Level& L = c->lv[l];
     void* pre = nullptr;
@@ -1085,6 +1137,7 @@ void rk_default_options(rk_options* o) {
     o->vc_streams = 2;
     o->z_chunk = 0;
     o->tile_shape = 0;
+    o->tail_nodes = 17 * 17 * 17;
 }
 
 int rk_workspace_bytes(const rk_mesh* mesh, int degree, int Q, const rk_options* opt, size_t* bytes) {
@@ -1267,6 +1320,7 @@ int rk_info(const rk_ctx* c, rk_info_t* o) {
         o->level_ts_store[l] = c->lv[l].ts_st;
     }
     o->krylov_cz = c->cz_pair;
+    o->tail_level = c->tail_level;
     return RK_OK;
 }
 

@@ -128,6 +128,33 @@ hipError_t launch_restrict(int k, int dtype, const void* fine, void* coarse, voi
 hipError_t launch_prolong_add(int k, int dtype, const void* coarse, void* fine, int nc, int nstage,
                               long long cstride, long long fstride, hipStream_t st);
 
+// The coarse end of a V-cycle in one launch (one workgroup per stage block):
+// levels lv[0..nlev) are consecutive multigrid levels, lv[0] the finest of
+// them.  Per level: the rhs b and the two iterate buffers x ("first") and y
+// ("second"), stage-0 bases of [Q][N3] vectors; the block scales
+// alpha_s Mref + beta_s Kref; the Chebyshev interval (theta, delta, sigma as
+// in the multi-launch path) and degree (the coarse degree on the last level).
+// On return the V-cycle result for lv[0].b is in lv[0].y if nlev > 1, else in
+// lv[0].x for an odd degree and lv[0].y for an even one.  scratch: per stage
+// sstride >= 4 n3max values, n3max >= lv[0].N3.
+constexpr int kTailMaxLevels = 8;
+struct TailLevel {
+    void* b = nullptr;
+    void* x = nullptr;
+    void* y = nullptr;
+    long long N3 = 0;
+    int n = 0, degree = 1;
+    double theta = 1.0, delta = 1.0, sigma = 1.0;
+    double alpha[RK_MAX_Q] = {}, beta[RK_MAX_Q] = {};
+};
+struct TailArgs {
+    TailLevel lv[kTailMaxLevels];
+    int nlev = 0, s0 = 0, dtype = RK_FP32;
+    void* scratch = nullptr;
+    long long sstride = 0, n3max = 0;
+};
+hipError_t launch_tail_vcycle(int k, const TailArgs& a, int nblocks, hipStream_t st);
+
 // x = cb D^-1 b (first Chebyshev step from a zero start), D = diag of the
 // diagonal-mix operator with scales sc, per stage; boundary entries 0.
 hipError_t launch_cheb_first(int k, int dtype, const StageScal& sc, const void* b, void* x,

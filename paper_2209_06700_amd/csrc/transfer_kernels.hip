@@ -29,24 +29,14 @@
 
 #include "element_data.h"
 #include "rk_internal.h"
+#include "transfer_rows.h"
 
 namespace rk {
 namespace {
 
-template <typename F, int... I>
-__device__ __forceinline__ void tfor_impl(F&& f, std::integer_sequence<int, I...>) {
-    (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void tfor(F&& f) {
-    tfor_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-// Pe[j][a]: fine node j (0..2k) of a coarse cell, coarse node a (0..k)
-template <int K, int J, int A>
-struct PE {
-    static constexpr double v = elem::Table<K>::d.P[J][A];
-};
+using xfer::PE;
+using xfer::rrow;
+using xfer::tfor;
 
 template <int K>
 struct PTile {
@@ -197,30 +187,6 @@ __global__ void __launch_bounds__(PTile<K>::NT) prolong_add_kernel(ProlongArgs<T
 #pragma unroll
         for (int q = 0; q < RPT; ++q) XY[0][q] = XY[K][q];
     }
-}
-
-// out[a], a = 0..k-1, of coarse cell E from w[u] = f(2(E-1)k + u), u = 0..4k
-template <int K, typename T>
-__device__ __forceinline__ void rrow(const T* w, T* out) {
-    T o = T(PE<K, 0, K>::v) * w[0];
-    tfor<2 * K - 1>([&](auto tm) {
-        constexpr int t = decltype(tm)::value + 1;
-        o = fma(T(PE<K, t, K>::v), w[t], o);
-    });
-    tfor<2 * K + 1>([&](auto tm) {
-        constexpr int t = decltype(tm)::value;
-        o = fma(T(PE<K, t, 0>::v), w[2 * K + t], o);
-    });
-    out[0] = o;
-    tfor<K - 1>([&](auto am) {
-        constexpr int a = decltype(am)::value + 1;
-        T q = T(PE<K, 0, a>::v) * w[2 * K];
-        tfor<2 * K>([&](auto tm) {
-            constexpr int t = decltype(tm)::value + 1;
-            q = fma(T(PE<K, t, a>::v), w[2 * K + t], q);
-        });
-        out[a] = q;
-    });
 }
 
 template <int K>

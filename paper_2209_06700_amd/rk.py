@@ -58,7 +58,8 @@ def rk_default_options(**kw) -> rk_options:
     """Options struct with the library defaults, overridden by keywords
     (precision, mode, rtol, max_iter, restart, cheb_degree, coarse_cheb_degree,
     cheb_range, eig_safety, eig_iterations, timing, method, deform, autotune,
-    deform_mg, vc_streams; eig_max is set by rk_create)."""
+    deform_mg, vc_streams, z_chunk, tile_shape, tail_nodes; eig_max is set by
+    rk_create)."""
     o = rk_options()
     LIB.rk_default_options(C.byref(o))
     for k, v in kw.items():
@@ -155,7 +156,7 @@ def rk_info(ctx: Context) -> dict:
                 clam=[complex(i.clam_re[j], i.clam_im[j]) for j in range(i.n_blocks)],
                 T=mat(i.T), U=mat(i.U), level_cz=list(i.level_cz[:nl]), krylov_cz=i.krylov_cz,
                 level_ts=list(i.level_ts[:nl]), level_cz_store=list(i.level_cz_store[:nl]),
-                level_ts_store=list(i.level_ts_store[:nl]))
+                level_ts_store=list(i.level_ts_store[:nl]), tail_level=i.tail_level)
 
 
 def rk_step(ctx: Context, t_n: float, y: torch.Tensor, G: torch.Tensor | None = None,

@@ -39,16 +39,24 @@ VCASES = [(8, 2, 2, 0.05, 3, 3), (4, 3, 3, 0.01, 2, 4), (16, 1, 2, 0.1, 3, 3), (
           (8, 4, 2, 0.01, 4, 1), (4, 4, 3, 0.01, 1, 2)]
 
 
+# tail_nodes: the default (the levels of at most 17^3 nodes in one launch:
+# every level of most cases here, the coarse levels of (4, 5) and (8, 4)),
+# and 0 (every level launches its own kernels)
+TAILS = {"tail": 17 ** 3, "launches": 0}
+
+
 @pytest.mark.parametrize("n,k,Q,tau,deg,cdeg", VCASES)
 @pytest.mark.parametrize("mode", ["batched", "per_stage"])
-def test_vcycle_parity_fp64(R, n, k, Q, tau, deg, cdeg, mode):
+@pytest.mark.parametrize("tail", sorted(TAILS))
+def test_vcycle_parity_fp64(R, n, k, Q, tau, deg, cdeg, mode, tail):
     from paper_2209_06700_amd.synthetic import random_vector
-    print(f"vcycle fp64 n={n} k={k} Q={Q} {mode}", flush=True)
+    print(f"vcycle fp64 n={n} k={k} Q={Q} {mode} {tail}", flush=True)
     tab, hier, mg = _oracle_mg(n, k, Q, tau, deg, cdeg)
     fine = hier.levels[0]
     N = n * k + 1
     opts = R.rk_default_options(cheb_degree=deg, coarse_cheb_degree=cdeg, cheb_range=15.0,
-                                mode=R.RK_BATCHED if mode == "batched" else R.RK_PER_STAGE)
+                                mode=R.RK_BATCHED if mode == "batched" else R.RK_PER_STAGE,
+                                tail_nodes=TAILS[tail])
     ctx = R.rk_create(n, k, Q, tau, opts, eig_max=list(mg.eig_max))
     try:
         b_np = random_vector((Q, N ** 3), seed=7 + n, zero_boundary_N=N)
@@ -85,13 +93,15 @@ def test_batched_and_per_stage_are_identical(R):
     assert torch.equal(outs[1][2], outs[3][2])
 
 
-@pytest.mark.parametrize("n,k,Q,tau", [(8, 2, 2, 0.05), (4, 4, 3, 0.01)])
-def test_vcycle_mixed_precision(R, n, k, Q, tau):
+@pytest.mark.parametrize("n,k,Q,tau", [(8, 2, 2, 0.05), (4, 4, 3, 0.01), (8, 4, 2, 0.01)])
+@pytest.mark.parametrize("tail", sorted(TAILS))
+def test_vcycle_mixed_precision(R, n, k, Q, tau, tail):
     from paper_2209_06700_amd.synthetic import random_vector
     tab, hier, mg = _oracle_mg(n, k, Q, tau, 3, 3)
     fine = hier.levels[0]
     N = n * k + 1
-    ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(precision=R.RK_PREC_MIXED), eig_max=list(mg.eig_max))
+    ctx = R.rk_create(n, k, Q, tau, R.rk_default_options(precision=R.RK_PREC_MIXED, tail_nodes=TAILS[tail]),
+                      eig_max=list(mg.eig_max))
     try:
         b_np = random_vector((Q, N ** 3), seed=11, zero_boundary_N=N).astype(np.float32)
         b = torch.tensor(b_np, device="cuda")
@@ -269,3 +279,35 @@ def test_autotune_picks_valid_chunks(R):
     assert torch.equal(y1, y2)
     s.close()
     plain.close()
+
+
+@pytest.mark.parametrize("n,k,Q,deg,cdeg,expect", [(32, 4, 4, 3, 3, 3), (16, 2, 3, 2, 4, 1), (24, 5, 2, 3, 2, 3),
+                                                   (8, 6, 3, 4, 1, 2), (7, 2, 2, 3, 3, 0), (64, 1, 2, 3, 3, 2)])
+def test_tail_agrees_with_the_launch_chain(R, n, k, Q, deg, cdeg, expect):
+    """The one-launch coarse end of the V-cycle against every level launching
+    its own kernels, on hierarchies whose tail starts below the fine level
+    (restriction into the tail's right-hand side, its result prolongated by
+    the launch chain) or at it, odd and even smoother and coarse degrees:
+    fp64 within 1e-13 and mixed within 1e-5 of the largest entry (the same
+    arithmetic summed in another order), and the tail level rk_info reports."""
+    from paper_2209_06700_amd.synthetic import random_vector
+    N = n * k + 1
+    print(f"tail n={n} k={k} Q={Q}", flush=True)
+    b64 = torch.tensor(random_vector((Q, N ** 3), seed=5 + n, zero_boundary_N=N), device="cuda")
+    eig = [2.0 + 0.05 * l for l in range(R.n_levels(n))]
+    for prec, dt, tol in ((R.RK_PREC_FP64, torch.float64, 1e-13), (R.RK_PREC_MIXED, torch.float32, 1e-5)):
+        outs = []
+        for tn in (17 ** 3, 0):
+            s = R.RadauIIA(n, k, Q, 0.01, precision=prec, cheb_degree=deg, coarse_cheb_degree=cdeg, tail_nodes=tn,
+                           eig_max=eig)
+            assert s.info["tail_level"] == (expect if tn else -1)
+            b = b64.to(dt)
+            x = torch.full_like(b, float("nan"))
+            s.vcycle(b, x)
+            torch.cuda.synchronize()
+            outs.append(x.double())
+            s.close()
+        scale = outs[1].abs().max().item()
+        assert torch.isfinite(outs[0]).all()
+        err = (outs[0] - outs[1]).abs().max().item()
+        assert err <= tol * scale, (prec, err / scale)
