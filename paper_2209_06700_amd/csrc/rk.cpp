@@ -113,6 +113,7 @@ struct rk_ctx {
     int n = 0, k = 0, Q = 0, N = 0;
     long long N3 = 0;
     double tau = 0.0, h = 0.0;
+    double length = 1.0;           // edge of the cube; h = length / n
     rk_options opt{};
     std::vector<double> eig_user;
     Tableau tab{};
@@ -301,6 +302,8 @@ size_t carve(rk_ctx& c, char* base) {
 int setup_sizes(rk_ctx& c, const rk_mesh* mesh, int degree, int Q, const rk_options* opt) {
     if (!mesh || mesh->n_cells < 1 || degree < 1 || degree > RK_MAX_DEGREE || Q < 1 || Q > RK_MAX_Q)
         return fail(nullptr, RK_EINVAL, "mesh, degree (1..6) or Q (1..9) out of range");
+    if (!(mesh->length > 0.0) || !std::isfinite(mesh->length))
+        return fail(nullptr, RK_EINVAL, "mesh length must be finite and > 0");
     // launch grids put (stage, z-plane) pairs in one grid dimension (<= 65535)
     // and operator kernels address a node plane with 32-bit byte offsets
     if ((long long)mesh->n_cells * degree + 1 > std::min(65535 / Q, 16384))
@@ -315,18 +318,21 @@ int setup_sizes(rk_ctx& c, const rk_mesh* mesh, int degree, int Q, const rk_opti
     c.Q = Q;
     c.N = c.n * c.k + 1;
     c.N3 = (long long)c.N * c.N * c.N;
-    c.h = 1.0 / c.n;
+    c.length = mesh->length;
+    c.h = c.length / c.n;
     c.pc = c.opt.precision == RK_PREC_MIXED ? RK_FP32 : RK_FP64;
     c.cplx = c.opt.method == RK_METHOD_COMPLEX;
     c.deformed = c.opt.deform != 0.0;
     c.dmg = c.deformed && c.opt.deform_mg == 1;
+    if (c.deformed && c.length != 1.0)
+        return fail(nullptr, RK_EINVAL, "deformed meshes are defined on the unit cube: mesh length must be 1");
     c.lv.clear();
     for (int m : level_cells(c.n)) {
         Level L;
         L.n = m;
         L.N = m * c.k + 1;
         L.N3 = (long long)L.N * L.N * L.N;
-        L.h = 1.0 / m;
+        L.h = c.length / m;
         c.lv.push_back(L);
     }
     // the one-launch coarse end: affine-mesh levels of at most tail_nodes
@@ -388,6 +394,8 @@ int op(rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, vo
     // operators of every level in the preconditioner precision
     if (c->opt.z_chunk > 0) {
         L.cz = c->opt.z_chunk;
+        // the fixed tile shape applies to the fp32 diagonal-mix kernels
+        if (!cf.pair && dtype == RK_FP32) L.ts = c->opt.tile_shape;
     } else if (cf.pair) {
         if (n == c->n && dtype == RK_FP64) L.cz = c->cz_pair;
     } else if (dtype == c->pc) {
@@ -1509,6 +1517,8 @@ namespace {
 int check_deformed(const rk_mesh* mesh, int degree, int dtype) {
     if (!mesh || mesh->n_cells < 1 || degree < 1 || degree > RK_MAX_DEGREE)
         return fail(nullptr, RK_EINVAL, "mesh or degree (1..6) out of range");
+    if (mesh->length != 1.0)
+        return fail(nullptr, RK_EINVAL, "deformed meshes are defined on the unit cube: mesh length must be 1");
     if ((long long)mesh->n_cells * degree + 1 > 16384)
         return fail(nullptr, RK_EINVAL, "grid too large: need n_cells*degree + 1 <= 16384");
     if (dtype != RK_FP64 && dtype != RK_FP32) return fail(nullptr, RK_EINVAL, "bad dtype");
