@@ -108,8 +108,11 @@ extern "C" {
 
 typedef struct rk_ctx rk_ctx;
 
-/* Uniform mesh of [0,1]^3 with n_cells^3 hexahedra (n_cells = 2^L in Sec. 5;
-   any n_cells >= 1 here, with N = n_cells*degree + 1 <= 16384 and N*Q <= 65535).  Multigrid
+/* Uniform mesh of the cube [0,length]^3 with n_cells^3 hexahedra (Sec. 5: the
+   unit cube, n_cells = 2^L; here any length > 0, cell size h = length/n_cells,
+   so M scales with h^3 and K with h; the deformed-mesh calls and contexts with
+   deform != 0 take length = 1, the cube their mapping is defined on).  Any
+   n_cells >= 1, with N = n_cells*degree + 1 <= 16384 and N*Q <= 65535.  Multigrid
    levels halve n_cells while it is even, down to the odd part of n_cells
    (rk_info_t.n_levels, rk_info_t.level_cells).  An odd n_cells therefore has a
    single level: the "V-cycle" is then the Chebyshev-Jacobi coarse solve on
@@ -118,6 +121,7 @@ typedef struct rk_ctx rk_ctx;
    for n_cells = 15 against 16).  Use n_cells = m 2^L with a small odd m. */
 typedef struct {
     int32_t n_cells;
+    double  length;             /* edge of the cube, > 0 */
 } rk_mesh;
 
 typedef struct {
@@ -285,9 +289,15 @@ int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* cons
 int rk_apply_operator(rk_ctx* ctx, int form, int dtype, const void* d_u, void* d_v);
 
 /* x_i = one V-cycle for the block lam_i M + tau K applied to b_i, i = 1..Q,
-   on [Q][N^3] vectors (RK_METHOD_COMPLEX: for the PRESB matrix H of slot i).  dtype must be RK_FP32 for RK_PREC_MIXED contexts and
-   RK_FP64 otherwise.  Batched or per-stage as set in the options.  b and x
-   must not overlap.  Asynchronous. */
+   on [Q][N^3] vectors (RK_METHOD_COMPLEX: for the PRESB matrix H of slot i):
+   the geometric multigrid of Sec. 5 (levels halve n_cells, transfer by the
+   nested-space embedding and its transpose), V(nu,nu) with Chebyshev-Jacobi
+   smoothing of degree nu = cheb_degree and a Chebyshev-Jacobi coarse solve of
+   degree coarse_cheb_degree, one Chebyshev interval for all blocks (Sec. 5.4).
+   dtype must be RK_FP32 for RK_PREC_MIXED contexts and RK_FP64 otherwise.
+   Batched (all blocks in each launch, Sec. 3.4) or per-stage as set in the
+   options.  b's boundary entries must be 0; x's are written 0.  b and x must
+   not overlap.  Asynchronous. */
 int rk_vcycle(rk_ctx* ctx, int dtype, const void* d_b, void* d_x);
 
 /* z = P^-1 r (eq. irk:P) on fp64 [Q][N^3] vectors: basis change S^-1 (with

@@ -32,7 +32,10 @@ EXPORTS = ["rk_default_options", "rk_workspace_bytes", "rk_create", "rk_destroy"
 
 
 class rk_mesh(C.Structure):
-    _fields_ = [("n_cells", C.c_int32)]
+    _fields_ = [("n_cells", C.c_int32), ("length", C.c_double)]
+
+    def __init__(self, n_cells=0, length=1.0):
+        super().__init__(n_cells, length)
 
 
 class rk_options(C.Structure):

@@ -17,6 +17,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -85,6 +86,8 @@ extern "C" int rk_apply_operator_static(const rk_mesh* mesh, int degree, int Q, 
     using namespace rk;
     if (!mesh || mesh->n_cells < 1 || degree < 1 || degree > RK_MAX_DEGREE)
         return report_free_error(RK_EINVAL, "mesh or degree (1..6) out of range");
+    if (!(mesh->length > 0.0) || !std::isfinite(mesh->length))
+        return report_free_error(RK_EINVAL, "mesh length must be finite and > 0");
     if ((long long)mesh->n_cells * degree + 1 > 16384)
         return report_free_error(RK_EINVAL, "grid too large: need n_cells*degree + 1 <= 16384");
     if (Q < 1 || Q > RK_MAX_Q) return report_free_error(RK_EINVAL, "Q out of range (1..9)");
@@ -110,7 +113,7 @@ extern "C" int rk_apply_operator_static(const rk_mesh* mesh, int degree, int Q, 
 
     // v_s = alpha_s Mref uM_s + beta_s Kref uK_s with the cell size folded in
     // (h^3 for the mass term, h for the stiffness term), as in the context.
-    const double h = 1.0 / n, h3 = h * h * h;
+    const double h = mesh->length / n, h3 = h * h * h;
     OpLaunch L;
     L.k = degree;
     L.dtype = dtype;

@@ -71,8 +71,9 @@ def rk_default_options(**kw) -> rk_options:
     return o
 
 
-def rk_workspace_bytes(n_cells: int, degree: int, Q: int, opts: rk_options | None = None) -> int:
-    mesh = rk_mesh(n_cells)
+def rk_workspace_bytes(n_cells: int, degree: int, Q: int, opts: rk_options | None = None,
+                       length: float = 1.0) -> int:
+    mesh = rk_mesh(n_cells, length)
     out = C.c_size_t(0)
     _check(LIB.rk_workspace_bytes(C.byref(mesh), degree, Q, C.byref(opts) if opts else None, C.byref(out)))
     return out.value
@@ -109,9 +110,9 @@ def n_levels(n_cells: int) -> int:
 
 def rk_create(n_cells: int, degree: int, Q: int, tau: float, opts: rk_options | None = None,
               eig_max=None, device: str | torch.device = "cuda",
-              stream: torch.cuda.Stream | None = None) -> Context:
+              stream: torch.cuda.Stream | None = None, length: float = 1.0) -> Context:
     """Allocate the workspace (torch) and create a context on `stream`
-    (default: the current stream of `device`)."""
+    (default: the current stream of `device`) for the cube [0, length]^3."""
     opts = opts if opts is not None else rk_default_options()
     eig_arr = None
     if eig_max is not None:
@@ -120,14 +121,14 @@ def rk_create(n_cells: int, degree: int, Q: int, tau: float, opts: rk_options | 
             raise ValueError(f"eig_max needs {n_levels(n_cells)} values (one per level)")
         eig_arr = (C.c_double * len(vals))(*vals)
         opts.eig_max = C.cast(eig_arr, C.POINTER(C.c_double))
-    nbytes = rk_workspace_bytes(n_cells, degree, Q, opts)
+    nbytes = rk_workspace_bytes(n_cells, degree, Q, opts, length)
     dev = torch.device(device)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     # The workspace is used on the context stream only: allocate it there, so
     # that the caching allocator orders its reuse after that stream's work.
     with torch.cuda.stream(st):
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    mesh = rk_mesh(n_cells)
+    mesh = rk_mesh(n_cells, length)
     h = C.c_void_p()
     rc = LIB.rk_create(C.byref(mesh), degree, Q, float(tau), C.byref(opts), C.c_void_p(ws.data_ptr()),
                        nbytes, C.c_void_p(st.cuda_stream), C.byref(h))
@@ -285,7 +286,7 @@ def rk_deformed_apply(n_cells: int, degree: int, alpha, beta, geometry: torch.Te
 
 
 def rk_apply_operator_static(n_cells: int, degree: int, Q: int, tau: float, form: int, u: torch.Tensor,
-                             v: torch.Tensor, stream: torch.cuda.Stream | None = None):
+                             v: torch.Tensor, stream: torch.cuda.Stream | None = None, length: float = 1.0):
     """v = op(u) without a context or any allocation (the library's static
     scratch holds the mixed input of RK_OP_CALA / RK_OP_STAGE)."""
     ns = 1 if form in (RK_OP_K, RK_OP_M) else Q
@@ -293,7 +294,7 @@ def rk_apply_operator_static(n_cells: int, degree: int, Q: int, tau: float, form
     up = _vec(u, n, "u")
     vp = _vec(v, n, "v", u.dtype)
     st = stream if stream is not None else torch.cuda.current_stream(u.device)
-    _check(LIB.rk_apply_operator_static(C.byref(rk_mesh(n_cells)), degree, Q, float(tau), int(form),
+    _check(LIB.rk_apply_operator_static(C.byref(rk_mesh(n_cells, length)), degree, Q, float(tau), int(form),
                                         _dtype_code(u), up, vp, C.c_void_p(st.cuda_stream)))
 
 
@@ -316,10 +317,11 @@ class DeformedOperator:
 class RadauIIA:
     """Owner of one context: ``RadauIIA(n_cells, degree, Q, tau, **options)``."""
 
-    def __init__(self, n_cells, degree, Q, tau, eig_max=None, device="cuda", stream=None, **options):
+    def __init__(self, n_cells, degree, Q, tau, eig_max=None, device="cuda", stream=None, length=1.0,
+                 **options):
         self.opts = rk_default_options(**options)
         self.ctx = rk_create(n_cells, degree, Q, tau, self.opts, eig_max=eig_max, device=device,
-                             stream=stream)
+                             stream=stream, length=length)
         self.info = rk_info(self.ctx)
         self.N, self.Q = self.ctx.N, Q
 

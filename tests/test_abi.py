@@ -133,3 +133,19 @@ def test_step_batch_argument_checks_without_the_gpu():
     y = (C.c_void_p * 1)(None)
     assert L.rk_step_batch(ctx, 1, t, y, None, None, None, None, 1) == _lib.RK_EINVAL
     assert L.rk_step_batch(ctx, -1, t, y, None, None, None, None, 1) == _lib.RK_EINVAL
+
+
+def test_mesh_length_checked_without_the_gpu():
+    """rk_mesh.length must be finite and > 0, and 1 for deformed meshes."""
+    from paper_2209_06700_amd import _lib
+    from paper_2209_06700_amd import rk as R
+    lib = _lib.LIB
+    out = C.c_size_t(0)
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        assert lib.rk_workspace_bytes(C.byref(_lib.rk_mesh(4, bad)), 2, 2, None, C.byref(out)) == _lib.RK_EINVAL
+    assert lib.rk_workspace_bytes(C.byref(_lib.rk_mesh(4, 3.0)), 2, 2, None, C.byref(out)) == 0 and out.value > 0
+    opts = R.rk_default_options(deform=0.05)
+    assert lib.rk_workspace_bytes(C.byref(_lib.rk_mesh(4, 2.0)), 2, 2, C.byref(opts), C.byref(out)) == _lib.RK_EINVAL
+    assert b"unit cube" in lib.rk_last_error(None)
+    assert lib.rk_deformed_geometry_bytes(C.byref(_lib.rk_mesh(4, 2.0)), 2, _lib.RK_FP64,
+                                          C.byref(out)) == _lib.RK_EINVAL

@@ -160,3 +160,48 @@ def test_operator_parity_full_size_sampled(R, n, k, Q, dtype, form):
     g = got.reshape(Q, N, N, N)
     for face in (g[:, 0], g[:, -1], g[:, :, 0], g[:, :, -1], g[:, :, :, 0], g[:, :, :, -1]):
         assert not face.any()
+
+
+class _Scaled:
+    """The oracle's unit-cube matrices on the cube [0, L]^3: the element
+    integrals scale with h^3 (mass) and h (stiffness), so M_L = L^3 M and
+    K_L = L K."""
+
+    def __init__(self, p, L):
+        self.M, self.K = p.M * L ** 3, p.K * L
+        self.to_int, self.to_full = p.to_int, p.to_full
+
+
+@pytest.mark.parametrize("n,k,Q,L", [(4, 2, 3, 2.5), (3, 4, 2, 0.3), (5, 1, 2, 7.0)])
+def test_operator_parity_on_a_cube_of_other_length(R, n, k, Q, L):
+    """rk_mesh.length: every form on [0, L]^3 against the oracle's scaled
+    matrices (fp64, the small-mesh bar), and the allocation-free entry point
+    bitwise equal to the context on the same cube."""
+    from oracle.assemble import Problem
+    from oracle.tableau import RadauIIA
+    from paper_2209_06700_amd.synthetic import random_vector
+    tau = 0.013
+    N = n * k + 1
+    tab = RadauIIA(Q)
+    u_np = random_vector((Q, N ** 3), seed=7 * n + k, zero_boundary_N=N)
+    ref = _oracle_forms(_Scaled(Problem(n, k), L), tab, tau, u_np)
+    s = R.RadauIIA(n, k, Q, tau, length=L, eig_max=[1.0] * R.n_levels(n))
+    try:
+        assert abs(s.info["h"] - L / n) <= 1e-15 * L
+        u = torch.tensor(u_np, device="cuda")
+        for name, form in [("CALA", R.RK_OP_CALA), ("STAGE", R.RK_OP_STAGE), ("BLOCKS", R.RK_OP_BLOCKS),
+                           ("K", R.RK_OP_K), ("M", R.RK_OP_M)]:
+            ns = 1 if name in ("K", "M") else Q
+            uu = u.view(-1)[: ns * N ** 3]
+            v = torch.full((ns * N ** 3,), float("nan"), dtype=torch.float64, device="cuda")
+            s.apply_operator(form, uu, v)
+            w = torch.full_like(v, float("nan"))
+            R.rk_apply_operator_static(n, k, Q, tau, form, uu, w, length=L)
+            torch.cuda.synchronize()
+            assert torch.equal(v, w), name
+            got = v.cpu().numpy().reshape(ns, -1)
+            want, scale = ref[name]
+            err = np.abs(got - want)
+            assert (err <= 64 * np.finfo(np.float64).eps * scale + 1e-300).all(), (name, float(err.max()))
+    finally:
+        s.close()

@@ -231,3 +231,24 @@ def test_full_size_64cubed_q4_mixed_batched(R):
         solver.close()
         del y
         torch.cuda.empty_cache()
+
+
+def test_step_on_a_cube_of_other_length(R):
+    """rk_mesh.length: on [0, L]^3, M_L = L^3 M and K_L = L K, so without a
+    source the Radau IIA step with tau equals the unit-cube step with tau/L^2
+    (the stage system scales by L^3 throughout); both at rtol 1e-12, fp64 and
+    mixed precision, within 1e-9 of each other."""
+    from paper_2209_06700_amd.synthetic import fourier_field, grid_coords
+    n, k, Q, tau, L = 8, 2, 3, 0.004, 2.0
+    for prec in (R.RK_PREC_FP64, R.RK_PREC_MIXED):
+        ys = []
+        for length, t in ((L, tau), (1.0, tau / L ** 2)):
+            s = R.RadauIIA(n, k, Q, t, length=length, precision=prec, rtol=1e-12)
+            y = torch.tensor(fourier_field(grid_coords(s.info["nodes"], n), seed=3), device="cuda")
+            st = s.step(0.0, y)
+            assert st["rel_residual"] <= 1e-12
+            torch.cuda.synchronize()
+            ys.append(y.clone())
+            s.close()
+        rel = ((ys[0] - ys[1]).norm() / ys[1].norm()).item()
+        assert rel <= 1e-9, (prec, rel)
