@@ -57,7 +57,6 @@ HBM_PEAK_GBS = 8000.0
 # x 2 flop (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 OP_KERNEL = "op_kernel<4, float, MIX_DIAG, EPI_STORE>"
-OP_KERNEL_MANGLED = "_ZN2rk3dev9op_kernelILi4EfLi0ELi0EEEvNS0_6OpArgsIT0_EE"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -139,7 +138,7 @@ def traffic_record(fetch_csv, write_csv, cz, n=64, k=4, Q=4, reps=3, ts=0):
     total = 0.0
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _counter_rows(path, counter)
-        op = [v for nm, v in rows if nm.startswith(OP_KERNEL_MANGLED) or "op_kernel<4, float, 0, 0>" in nm]
+        op = [v for nm, v in rows if f"op_kernel<{k}, float, 0, 0, {ts}>" in nm]
         cp = [v for nm, v in rows if COPY_KERNEL in nm]
         if len(op) < reps or not cp:
             raise SystemExit(f"{path}: no {counter} rows for the operator or the copy kernel")
