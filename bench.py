@@ -390,7 +390,8 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20, autotune=1):
     4..48 (values with a multigrid hierarchy: n = 2^j or 3 * 2^j), degree
     U{1..6}, Q U{1..5}, tau log-uniform in [1e-4, 1e-1], mixed precision,
     seeded Fourier data.  The problems are spread over the streams by load
-    (largest first, each onto the stream with the fewest stage-DoFs so far).
+    (largest first, each onto the least loaded stream, the load of a problem
+    being max(stage-DoFs, 8M)).
     Timed once concurrently (rk_step_batch, one host thread per stream) and
     once one problem after another."""
     import numpy as np
@@ -404,14 +405,15 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20, autotune=1):
         tau = float(10 ** rng.uniform(-4, -1))
         probs.append((n, k, Q, tau))
     sts = [torch.cuda.Stream() for _ in range(streams)]
-    # streams by load: problems largest first (stage-DoFs), each onto the
-    # stream with the fewest stage-DoFs so far
-    sdof = [Q * (n * k + 1) ** 3 for n, k, Q, _ in probs]
+    # streams by load: problems largest first, each onto the least loaded
+    # stream, by the estimated cost max(stage-DoFs, 8M) (below about 8M
+    # stage-DoFs a step is bound by launch and synchronisation latency)
+    cost = [max(Q * (n * k + 1) ** 3, 8 << 20) for n, k, Q, _ in probs]
     load, sid = [0] * streams, [0] * count
-    for i in sorted(range(count), key=lambda i: -sdof[i]):
+    for i in sorted(range(count), key=lambda i: -cost[i]):
         s = min(range(streams), key=lambda j: load[j])
         sid[i] = s
-        load[s] += sdof[i]
+        load[s] += cost[i]
     # one V-cycle stream per context (vc_streams = 1): the concurrent
     # contexts already fill the GPU, and split V-cycles measured slower here
     ctxs = [R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, rtol=1e-10, restart=restart,
@@ -441,7 +443,7 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20, autotune=1):
     torch.cuda.empty_cache()
     return {"problems": count, "recipe": f"default_rng({seed}): n in {list(BATCH_CELLS)}, k U{{1..6}}, "
                                          f"Q U{{1..5}}, tau log-uniform [1e-4, 1e-1], mixed, rtol 1e-10, vc_streams 1, "
-                                         f"restart {restart}, streams assigned by load",
+                                         f"restart {restart}, streams assigned by load max(stage-DoFs, 8M)",
             "stage_dofs": sdofs, "streams": streams, "autotune": autotune, "s_concurrent": t_conc,
             "s_sequential": t_seq,
             "speedup": t_seq / t_conc, "stage_dof_steps_per_s": sdofs / t_conc,

@@ -272,8 +272,10 @@ int rk_step(rk_ctx* ctx, double t_n, double* d_y, const double* d_G, const doubl
    per entry; at most 16), each on its context's own stream, so entries on
    different streams overlap on the GPU.  Entries whose contexts share a
    stream run on one thread, in input order; the streams are handed to the
-   threads largest first (by the stage-DoFs N^3 Q of their contexts), each
-   to the least loaded thread.  A context must appear at most once.  Every entry is attempted; per-entry codes
+   threads largest first, each to the least loaded thread, by the sum over
+   their contexts of max(N^3 Q, 2^23): below about 8M stage-DoFs a step costs
+   its launch and synchronisation latency more than its size.  A context must
+   appear at most once.  Every entry is attempted; per-entry codes
    go to h_codes, and the return value is the first failing entry's code
    (RK_OK if all succeeded).  Errors of an entry are reported by
    rk_last_error(ctx[i]). */

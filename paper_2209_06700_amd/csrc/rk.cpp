@@ -1450,6 +1450,11 @@ int rk_step(rk_ctx* c, double t_n, double* y, const double* G, const double* gam
     return RK_OK;
 }
 
+// Stage-DoFs below which a step costs about as much as a step of this size
+// (measured on the 64-problem uneven batch: balancing streams by
+// max(stage-DoFs, 8M) beat balancing by stage-DoFs by 5-8%).
+constexpr double kLatencyFloor = 8.0 * (1 << 20);
+
 int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* const* y, const double* const* G,
                   const double* gamma, rk_stats* stats, int* codes, int threads) {
     if (count < 0 || (count > 0 && (!ctx || !t_n || !y))) return fail(nullptr, RK_EINVAL, "bad batch arguments");
@@ -1465,8 +1470,10 @@ int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* cons
     std::vector<int> rc(count, RK_OK);
     // Entries are grouped by their context's stream (contexts that share a
     // stream run on one worker, in input order).  The streams go to the
-    // workers largest first, each to the least loaded worker, by the
-    // stage-DoFs of their contexts.
+    // workers largest first, each to the least loaded worker, by an estimated
+    // cost per step: the stage-DoFs of each context, but at least
+    // kLatencyFloor (below that a step is bound by its launch and
+    // synchronisation latency, not by its size).
     std::vector<hipStream_t> streams;
     std::vector<std::vector<int>> members;
     std::vector<double> cost;
@@ -1475,7 +1482,7 @@ int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* cons
         while (s < streams.size() && streams[s] != ctx[i]->stream) ++s;
         if (s == streams.size()) { streams.push_back(ctx[i]->stream); members.emplace_back(); cost.push_back(0.0); }
         members[s].push_back(i);
-        cost[s] += (double)ctx[i]->N3 * ctx[i]->Q;
+        cost[s] += std::max((double)ctx[i]->N3 * ctx[i]->Q, kLatencyFloor);
     }
     std::vector<int> order(streams.size());
     for (size_t s = 0; s < order.size(); ++s) order[s] = (int)s;
