@@ -93,7 +93,14 @@ struct Tile {
     // fewer resident workgroups per CU, which measured slower)
     static constexpr int CY = 8;
     static constexpr int TY = CY * K;                       // owned nodes in y
-    static constexpr int NT = TX * CY;                      // threads
+    // Pencil split: for k >= 5 the K rows of a y-pencil are shared by two
+    // threads (rows 0..R-1 and R..K-1), which halves the per-thread
+    // accumulators and y-pass outputs; each half is a whole number of waves,
+    // so the two halves never share a wave.
+    static constexpr int SPL = K >= 5 ? 2 : 1;
+    static constexpr int R = (K + SPL - 1) / SPL;           // pencil rows per thread
+    static constexpr int NTH = SPL == 1 ? TX * CY : (TX * CY + 63) / 64 * 64;   // threads per half
+    static constexpr int NT = SPL * NTH;                    // threads
     static constexpr int RW = TX + K + 1;                   // staged input width
     // LDS pitches are 2 (mod 4): lanes of a 16-lane group then read
     // adjacent pairs (ds_read2) from distinct banks
@@ -145,6 +152,38 @@ __device__ __forceinline__ void row_apply(const T* w, T* out) {
     });
 }
 
+// out[i] = (E w)[A0 + i], i < RR, for rows A0 + i < K of the element (row 0
+// the shared vertex, as in row_apply; rows >= 1 read only w[K..2K]); rows
+// past K are 0.
+template <int K, int W, int A0, int RR, typename T>
+__device__ __forceinline__ void row_apply_rows(const T* w, T* out) {
+    cfor<RR>([&](auto im) {
+        constexpr int a = A0 + decltype(im)::value;
+        if constexpr (a == 0) {
+            T o = T(EC<K, W, K, 0>::v) * w[0];
+            cfor<K - 1>([&](auto bm) {
+                constexpr int b = decltype(bm)::value + 1;
+                o = fma(T(EC<K, W, K, b>::v), w[b], o);
+            });
+            o = fma(T(EC<K, W, K, K>::v + EC<K, W, 0, 0>::v), w[K], o);
+            cfor<K>([&](auto bm) {
+                constexpr int b = decltype(bm)::value + 1;
+                o = fma(T(EC<K, W, 0, b>::v), w[K + b], o);
+            });
+            out[decltype(im)::value] = o;
+        } else if constexpr (a < K) {
+            T q = T(EC<K, W, a, 0>::v) * w[K];
+            cfor<K>([&](auto bm) {
+                constexpr int b = decltype(bm)::value + 1;
+                q = fma(T(EC<K, W, a, b>::v), w[K + b], q);
+            });
+            out[decltype(im)::value] = q;
+        } else {
+            out[decltype(im)::value] = T(0);
+        }
+    });
+}
+
 // 1D diagonals at a runtime local index r in [0, K)
 template <int K, int W, typename T>
 __device__ __forceinline__ T diag_rt(int r) {
@@ -172,6 +211,7 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
     constexpr int P = K + 1;
     constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, RX = TL::RX, RY = TL::RY;
     constexpr int XP = TL::XP, CX = TL::CX;
+    constexpr int SPL = TL::SPL, R = TL::R, NTH = TL::NTH;
     constexpr int NU = MIX == MIX_PAIR ? 2 : 1;
     constexpr bool CHEB = EPI == EPI_CHEB || EPI == EPI_CHEB1;
     constexpr bool INB = EPI == EPI_CHEB1;               // input x1 = c0 D^-1 b, formed from b
@@ -201,8 +241,15 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
     const int TZ = CZ * K;
     const int X0 = itx * TX, Y0 = ity * TY, E0 = icz * CZ, Z0 = E0 * K;
     const int tid = threadIdx.x;
-    const int tx = tid % TX, py = tid / TX;
-    const int gx = X0 + tx, gy0 = Y0 + py * K;
+    // pencil half h (uniform per wave) and this thread's x column and rows
+    // a0 .. a0 + nr - 1 of y-pencil py; threads past the tile's TX CY columns
+    // (the padding of a half to whole waves) own no column
+    const int h = SPL == 1 ? 0 : tid / NTH;
+    const int tl = tid - h * NTH;
+    const bool has_col = SPL == 1 || tl < TX * TL::CY;
+    const int tx = tl % TX, py = tl / TX;
+    const int a0 = h * R, nr = K - a0 < R ? K - a0 : R;
+    const int gx = X0 + tx, gy0 = Y0 + py * K + a0;
     // vs may alias p.xo (in-place Chebyshev update), so it is not restrict.
     T* vs = p.v + (long long)s * p.stride;
     // 32-bit in-plane offset of this thread's first pencil node, and the same
@@ -214,12 +261,12 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
     // Tiles that own only far-boundary nodes: write the zeros and leave.
     if (X0 >= nK || Y0 >= nK || Z0 >= nK) {
         const int z1 = min(Z0 + TZ, N);
-        if (gx < N)
+        if (has_col && gx < N)
             for (int z = Z0; z < z1; ++z) {
                 T* pl = vs + z * NN;
 #pragma unroll
-                for (int a = 0; a < K; ++a)
-                    if (gy0 + a < N) pl[colbase + (unsigned)(a * N)] = T(0);
+                for (int a = 0; a < R; ++a)
+                    if (a < nr && gy0 + a < N) pl[colbase + (unsigned)(a * N)] = T(0);
             }
         return;
     }
@@ -306,8 +353,8 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
         }
     };
 
-    T acc[P][K];
-    T sv[K], tv[K];
+    T acc[P][R];
+    T sv[R], tv[R];
 
     // x-pass of the plane staged in sU[buf] -> sX1/sX2[buf]
     auto xpass = [&](int buf) __attribute__((always_inline)) {
@@ -350,21 +397,45 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
             }
         }
     };
-    // y-pass of sX1/sX2[buf] for this thread's pencil -> sv, tv
+    // y-pass of sX1/sX2[buf] for this thread's pencil rows -> sv, tv
+    // (rows A0 .. A0 + R - 1; rows >= 1 read only the element's own K + 1
+    // inputs)
+    auto ypass_rows = [&](const T* X1, const T* X2, int cb, auto a0m) __attribute__((always_inline)) {
+        constexpr int A0 = decltype(a0m)::value;
+        constexpr int J0 = A0 == 0 ? 0 : K;
+        T w1[2 * K + 1], w2[2 * K + 1], m1[R], k2[R];
+#pragma unroll
+        for (int j = 0; j <= 2 * K; ++j) {
+            w1[j] = j >= J0 ? X1[cb + j] : T(0);
+            w2[j] = j >= J0 ? X2[cb + j] : T(0);
+        }
+        row_apply_rows<K, 0, A0, R, T>(w1, m1);
+        row_apply_rows<K, 1, A0, R, T>(w2, k2);
+        row_apply_rows<K, 0, A0, R, T>(w2, tv);
+#pragma unroll
+        for (int a = 0; a < R; ++a) sv[a] = m1[a] + k2[a];
+    };
     auto ypass = [&](int buf) __attribute__((always_inline)) {
         const T* X1 = sX1 + buf * XSZ;
         const T* X2 = sX2 + buf * XSZ;
-        T w1[2 * K + 1], w2[2 * K + 1], m1[K], k2[K];
+        if constexpr (SPL == 1) {
+            T w1[2 * K + 1], w2[2 * K + 1], m1[K], k2[K];
 #pragma unroll
-        for (int j = 0; j <= 2 * K; ++j) {
-            w1[j] = X1[tx * XP + py * K + j];
-            w2[j] = X2[tx * XP + py * K + j];
+            for (int j = 0; j <= 2 * K; ++j) {
+                w1[j] = X1[tx * XP + py * K + j];
+                w2[j] = X2[tx * XP + py * K + j];
+            }
+            row_apply<K, 0, T>(w1, m1);
+            row_apply<K, 1, T>(w2, k2);
+            row_apply<K, 0, T>(w2, tv);
+#pragma unroll
+            for (int a = 0; a < K; ++a) sv[a] = m1[a] + k2[a];
+        } else {
+            if (!has_col) return;
+            const int cb = tx * XP + py * K;
+            if (h == 0) ypass_rows(X1, X2, cb, std::integral_constant<int, 0>{});
+            else ypass_rows(X1, X2, cb, std::integral_constant<int, R>{});
         }
-        row_apply<K, 0, T>(w1, m1);
-        row_apply<K, 1, T>(w2, k2);
-        row_apply<K, 0, T>(w2, tv);
-#pragma unroll
-        for (int a = 0; a < K; ++a) sv[a] = m1[a] + k2[a];
     };
 
     // acc[c][a] += Mhat[c][B] sv[a] + Khat[c][B] tv[a]  (B compile-time)
@@ -373,7 +444,7 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
         cfor<P>([&](auto cm) {
             constexpr int c = decltype(cm)::value;
 #pragma unroll
-            for (int a = 0; a < K; ++a)
+            for (int a = 0; a < R; ++a)
                 acc[c][a] = fma(T(EC<K, 0, c, B>::v), sv[a], fma(T(EC<K, 1, c, B>::v), tv[a], acc[c][a]));
         });
     };
@@ -382,13 +453,13 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
         cfor<P>([&](auto cm) {
             constexpr int c = decltype(cm)::value;
 #pragma unroll
-            for (int a = 0; a < K; ++a)
+            for (int a = 0; a < R; ++a)
                 acc[c][a] = fma(T(EC<K, 0, c, 0>::v), sv[a], T(EC<K, 1, c, 0>::v) * tv[a]);
         });
     };
 
     // Epilogue data.  Boundary status of the thread's nodes in x and y.
-    const bool colok = gx < N;
+    const bool colok = has_col && gx < N;
     const bool xbnd = gx == 0 || gx == nK;
     T dmx = T(0), dkx = T(0);
     if (CHEB) {
@@ -416,7 +487,7 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
 
     const int E1 = min(E0 + CZ, n);                    // chunk elements E0 .. E1-1
     // Pencils whose nodes are all interior in x and y take the branch-free path.
-    const bool pencil_inner = colok && !xbnd && gy0 > 0 && gy0 + K - 1 < nK;
+    const bool pencil_inner = colok && !xbnd && gy0 > 0 && gy0 + nr - 1 < nK;
     // Chebyshev update x + ca (x - x_prev) + cb D^-1 (b - A x) at one node
     // (rD = 1/D); x = c0 D^-1 b for the fused first step, x_prev = c0 D^-1 b
     // when the previous iterate is the first one.
@@ -483,6 +554,77 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
         }
     };
 
+    // Write this thread's rows A0 .. A0 + R - 1 (those < K) of the K
+    // completed output planes of element e.  Per output plane the epilogue
+    // loads of its rows are issued together before any use.
+    auto flush_rows = [&](int e, auto a0m) __attribute__((always_inline)) {
+        constexpr int A0 = decltype(a0m)::value;
+        if (pencil_inner && e > 0) {
+            cfor<K>([&](auto cm) {
+                constexpr int c = decltype(cm)::value;
+                const long long zo = (long long)(e * K + c) * NN;
+                T lb[R], lx[R], lo[R];
+                if (EPI != EPI_STORE) {
+                    cfor<R>([&](auto am) {
+                        constexpr int a = decltype(am)::value;
+                        if constexpr (A0 + a < K) {
+                            const long long ro = zo + (long long)a * N;
+                            lb[a] = at(bs, ro);
+                            if (CHEB) {
+                                lx[a] = INB ? T(0) : at(us, ro);
+                                lo[a] = xos ? at(xos, ro) : T(0);
+                            }
+                        }
+                    });
+                }
+                cfor<R>([&](auto am) {
+                    constexpr int a = decltype(am)::value;
+                    if constexpr (A0 + a < K) {
+                        const long long ro = zo + (long long)a * N;     // uniform row offset
+                        const T av = acc[c][a];
+                        T out;
+                        if (EPI == EPI_STORE) out = av;
+                        else if (EPI == EPI_RESID) out = lb[a] - av;
+                        else out = cheb_update(lb[a], lx[a], lo[a], av,
+                                               recip(jac(cm, std::integral_constant<int, A0 + a>{})));
+                        *reinterpret_cast<T*>(reinterpret_cast<char*>(vs + ro) + colbyte) = out;
+                    }
+                });
+            });
+            return;
+        }
+        if (!colok) return;
+        cfor<K>([&](auto cm) {
+            constexpr int c = decltype(cm)::value;
+            const int z = e * K + c;
+            const long long zo = (long long)z * NN;
+            cfor<R>([&](auto am) {
+                constexpr int a = decltype(am)::value;
+                if constexpr (A0 + a < K) {
+                    const int y = gy0 + a;
+                    if (y < N) {
+                        const unsigned off = colbase + (unsigned)(a * N);
+                        const bool bnd = z == 0 || xbnd || y == 0 || y == nK;
+                        T out = T(0);
+                        if (!bnd) {
+                            const T av = acc[c][a];
+                            const long long g = zo + off;
+                            if (EPI == EPI_STORE) out = av;
+                            else if (EPI == EPI_RESID) out = bs[g] - av;
+                            else {
+                                const T x = INB ? T(0) : us[g];
+                                const T xo = xos ? xos[g] : T(0);
+                                out = cheb_update(bs[g], x, xo, av,
+                                                  recip(jac(cm, std::integral_constant<int, A0 + a>{})));
+                            }
+                        }
+                        (vs + zo)[off] = out;
+                    }
+                }
+            });
+        });
+    };
+
     // Write the K completed output planes of element e.  Per output plane the
     // epilogue loads of its K nodes are issued together before any use.
     auto flush = [&](int e) __attribute__((always_inline)) {
@@ -507,62 +649,12 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
             });
             return;
         }
-        if (pencil_inner && e > 0) {
-            cfor<K>([&](auto cm) {
-                constexpr int c = decltype(cm)::value;
-                const long long zo = (long long)(e * K + c) * NN;
-                T lb[K], lx[K], lo[K];
-                if (EPI != EPI_STORE) {
-                    cfor<K>([&](auto am) {
-                        constexpr int a = decltype(am)::value;
-                        const long long ro = zo + (long long)a * N;
-                        lb[a] = at(bs, ro);
-                        if (CHEB) {
-                            lx[a] = INB ? T(0) : at(us, ro);
-                            lo[a] = xos ? at(xos, ro) : T(0);
-                        }
-                    });
-                }
-                cfor<K>([&](auto am) {
-                    constexpr int a = decltype(am)::value;
-                    const long long ro = zo + (long long)a * N;     // uniform row offset
-                    const T av = acc[c][a];
-                    T out;
-                    if (EPI == EPI_STORE) out = av;
-                    else if (EPI == EPI_RESID) out = lb[a] - av;
-                    else out = cheb_update(lb[a], lx[a], lo[a], av, recip(jac(cm, am)));
-                    *reinterpret_cast<T*>(reinterpret_cast<char*>(vs + ro) + colbyte) = out;
-                });
-            });
-            return;
+        if constexpr (SPL == 1) {
+            flush_rows(e, std::integral_constant<int, 0>{});
+        } else {
+            if (h == 0) flush_rows(e, std::integral_constant<int, 0>{});
+            else flush_rows(e, std::integral_constant<int, R>{});
         }
-        if (!colok) return;
-        cfor<K>([&](auto cm) {
-            constexpr int c = decltype(cm)::value;
-            const int z = e * K + c;
-            const long long zo = (long long)z * NN;
-            cfor<K>([&](auto am) {
-                constexpr int a = decltype(am)::value;
-                const int y = gy0 + a;
-                if (y < N) {
-                    const unsigned off = colbase + (unsigned)(a * N);
-                    const bool bnd = z == 0 || xbnd || y == 0 || y == nK;
-                    T out = T(0);
-                    if (!bnd) {
-                        const T av = acc[c][a];
-                        const long long g = zo + off;
-                        if (EPI == EPI_STORE) out = av;
-                        else if (EPI == EPI_RESID) out = bs[g] - av;
-                        else {
-                            const T x = INB ? T(0) : us[g];
-                            const T xo = xos ? xos[g] : T(0);
-                            out = cheb_update(bs[g], x, xo, av, recip(jac(cm, am)));
-                        }
-                    }
-                    (vs + zo)[off] = out;
-                }
-            });
-        });
     };
 
     // z-accumulation of the plane just y-passed.  B is the plane's index
@@ -582,12 +674,12 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
             zacc(bm);
             if constexpr (B == K) {
                 if (e >= E0) flush(e);
-                T carry[K];
+                T carry[R];
 #pragma unroll
-                for (int a = 0; a < K; ++a) carry[a] = acc[K][a];
+                for (int a = 0; a < R; ++a) carry[a] = acc[K][a];
                 zinit();
 #pragma unroll
-                for (int a = 0; a < K; ++a) acc[0][a] += carry[a];
+                for (int a = 0; a < R; ++a) acc[0][a] += carry[a];
                 ++e;
                 if constexpr (PF) pf_fold(std::integral_constant<int, 0>{});
             }
@@ -668,12 +760,12 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
             }
             if (b == K) {
                 if (e >= E0) flush(e);
-                T carry[K];
+                T carry[R];
 #pragma unroll
-                for (int a = 0; a < K; ++a) carry[a] = acc[K][a];
+                for (int a = 0; a < R; ++a) carry[a] = acc[K][a];
                 zinit();
 #pragma unroll
-                for (int a = 0; a < K; ++a) acc[0][a] += carry[a];
+                for (int a = 0; a < R; ++a) acc[0][a] += carry[a];
                 ++e;
                 b = 0;
             }
@@ -698,8 +790,8 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
     if (E0 + CZ > n && colok) {
         T* pl = vs + (long long)nK * NN;
 #pragma unroll
-        for (int a = 0; a < K; ++a)
-            if (gy0 + a < N) pl[colbase + (unsigned)(a * N)] = T(0);
+        for (int a = 0; a < R; ++a)
+            if (a < nr && gy0 + a < N) pl[colbase + (unsigned)(a * N)] = T(0);
     }
 }
 

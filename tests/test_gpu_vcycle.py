@@ -173,15 +173,16 @@ def test_setup_tableau_matches_oracle(R, Q):
         assert np.abs(got - want).max() <= tol * scale, (key, np.abs(got - want).max())
 
 
-@pytest.mark.parametrize("n", [8, 24])
-def test_results_do_not_depend_on_the_z_chunk(R, n):
+@pytest.mark.parametrize("n,k", [(8, 3), (24, 3), (6, 5), (4, 6)])
+def test_results_do_not_depend_on_the_z_chunk(R, n, k):
     """The operator kernel's z-chunk length and x-y tile shape (tuned per
     level by the autotuner) change only the work decomposition: V-cycles
     (every epilogue and the transfers), the block operator and the pair
     operator give bitwise equal results for chunks of 1, 2 and 16 elements,
-    and (fp32 preconditioner) for both tile shapes."""
+    and (fp32 preconditioner) for both tile shapes; k = 5, 6 with two threads
+    per y-pencil."""
     from paper_2209_06700_amd.synthetic import random_vector
-    k, Q, tau = 3, 3, 0.02
+    Q, tau = 3, 0.02
     N = n * k + 1
     b = random_vector((Q, N ** 3), seed=9, zero_boundary_N=N)
     outs = {}
