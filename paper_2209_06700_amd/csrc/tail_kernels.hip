@@ -13,11 +13,13 @@
 // rotation, so the result lands where the caller expects it.
 //
 // Every operator application is sum factorisation over the whole level in
-// three passes through a per-block scratch (the 1D banded global matrices
-// along x, then y, then z, with the epilogue fused into the z pass), each pass
-// ended by a workgroup barrier; the transfers are three 1D passes each.  The
-// level vectors stay in the context's level buffers ([Q][N^3], x fastest);
-// the data of these levels are a few hundred kilobytes and stay in the caches.
+// three passes through a per-block scratch of four arrays (the 1D banded
+// global matrices along x, then y, then z, with the epilogue fused into the z
+// pass), each pass ended by a workgroup barrier; the transfers are three 1D
+// passes each.  The scratch lives in LDS for levels of up to 17^3 nodes,
+// else in memory.  The level vectors stay in the context's level buffers
+// ([Q][N^3], x fastest); the data of these levels are a few hundred kilobytes
+// and stay in the caches.
 //
 // Dirichlet conditions: inputs are read as zero on boundary nodes, and every
 // vector the kernel writes gets zeros on its boundary nodes.
@@ -345,10 +347,21 @@ struct Tail {
     }
 };
 
-template <int K, typename T>
+// Levels of up to kTailLdsNodes nodes keep the four scratch arrays in LDS
+// (4 * 17^3 values: 79 KB in fp32, 157 KB in fp64, within gfx950's 160 KB per
+// workgroup); larger first levels use the per-block scratch in memory.
+constexpr int kTailLdsNodes = 17 * 17 * 17;
+
+template <int K, typename T, bool LDS>
 __global__ void __launch_bounds__(kTailThreads) tail_vcycle_kernel(TailArgs a) {
     const int s = a.s0 + blockIdx.x;
-    T* scratch = static_cast<T*>(a.scratch) + (long long)s * a.sstride;
+    T* scratch;
+    if constexpr (LDS) {
+        __shared__ T lds[4 * kTailLdsNodes];
+        scratch = lds;
+    } else {
+        scratch = static_cast<T*>(a.scratch) + (long long)s * a.sstride;
+    }
     Tail<K, T> t(a, s, scratch, a.n3max);
     auto at = [&](void* base, const TailLevel& L) { return static_cast<T*>(base) + (long long)s * L.N3; };
     // down: pre-smoothing (result in `first`), residual into `second`, restriction
@@ -381,8 +394,14 @@ __global__ void __launch_bounds__(kTailThreads) tail_vcycle_kernel(TailArgs a) {
 
 template <int K>
 hipError_t launch_tail_k(const TailArgs& a, int nblocks, hipStream_t st) {
-    if (a.dtype == RK_FP64) tail_vcycle_kernel<K, double><<<nblocks, kTailThreads, 0, st>>>(a);
-    else tail_vcycle_kernel<K, float><<<nblocks, kTailThreads, 0, st>>>(a);
+    const bool lds = a.n3max <= kTailLdsNodes;
+    if (a.dtype == RK_FP64) {
+        if (lds) tail_vcycle_kernel<K, double, true><<<nblocks, kTailThreads, 0, st>>>(a);
+        else tail_vcycle_kernel<K, double, false><<<nblocks, kTailThreads, 0, st>>>(a);
+    } else {
+        if (lds) tail_vcycle_kernel<K, float, true><<<nblocks, kTailThreads, 0, st>>>(a);
+        else tail_vcycle_kernel<K, float, false><<<nblocks, kTailThreads, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 

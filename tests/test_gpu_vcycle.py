@@ -282,15 +282,19 @@ def test_autotune_picks_valid_chunks(R):
     plain.close()
 
 
-@pytest.mark.parametrize("n,k,Q,deg,cdeg,expect", [(32, 4, 4, 3, 3, 3), (16, 2, 3, 2, 4, 1), (24, 5, 2, 3, 2, 3),
-                                                   (8, 6, 3, 4, 1, 2), (7, 2, 2, 3, 3, 0), (64, 1, 2, 3, 3, 2)])
-def test_tail_agrees_with_the_launch_chain(R, n, k, Q, deg, cdeg, expect):
+@pytest.mark.parametrize("n,k,Q,deg,cdeg,expect,tn", [
+    (32, 4, 4, 3, 3, 3, 17 ** 3), (16, 2, 3, 2, 4, 1, 17 ** 3), (24, 5, 2, 3, 2, 3, 17 ** 3),
+    (8, 6, 3, 4, 1, 2, 17 ** 3), (7, 2, 2, 3, 3, 0, 17 ** 3), (64, 1, 2, 3, 3, 2, 17 ** 3),
+    (32, 4, 4, 3, 3, 2, 33 ** 3), (8, 3, 2, 3, 2, 0, 25 ** 3)])
+def test_tail_agrees_with_the_launch_chain(R, n, k, Q, deg, cdeg, expect, tn):
     """The one-launch coarse end of the V-cycle against every level launching
     its own kernels, on hierarchies whose tail starts below the fine level
     (restriction into the tail's right-hand side, its result prolongated by
-    the launch chain) or at it, odd and even smoother and coarse degrees:
-    fp64 within 1e-13 and mixed within 1e-5 of the largest entry (the same
-    arithmetic summed in another order), and the tail level rk_info reports."""
+    the launch chain) or at it, odd and even smoother and coarse degrees,
+    with the tail's scratch in LDS (first tail level of at most 17^3 nodes) or
+    in memory (larger thresholds): fp64 within 1e-13 and mixed within 1e-5 of
+    the largest entry (the same arithmetic summed in another order), and the
+    tail level rk_info reports."""
     from paper_2209_06700_amd.synthetic import random_vector
     N = n * k + 1
     print(f"tail n={n} k={k} Q={Q}", flush=True)
@@ -298,10 +302,10 @@ def test_tail_agrees_with_the_launch_chain(R, n, k, Q, deg, cdeg, expect):
     eig = [2.0 + 0.05 * l for l in range(R.n_levels(n))]
     for prec, dt, tol in ((R.RK_PREC_FP64, torch.float64, 1e-13), (R.RK_PREC_MIXED, torch.float32, 1e-5)):
         outs = []
-        for tn in (17 ** 3, 0):
-            s = R.RadauIIA(n, k, Q, 0.01, precision=prec, cheb_degree=deg, coarse_cheb_degree=cdeg, tail_nodes=tn,
+        for t in (tn, 0):
+            s = R.RadauIIA(n, k, Q, 0.01, precision=prec, cheb_degree=deg, coarse_cheb_degree=cdeg, tail_nodes=t,
                            eig_max=eig)
-            assert s.info["tail_level"] == (expect if tn else -1)
+            assert s.info["tail_level"] == (expect if t else -1)
             b = b64.to(dt)
             x = torch.full_like(b, float("nan"))
             s.vcycle(b, x)
