@@ -19,9 +19,12 @@ def R():
 
 
 # (n, k, Q, tau, precision)
+# (small problems whose V-cycle is one launch of the coarse-level kernel, and
+# problems of 32^3 and 48^3 cells with several levels above it)
 PROBLEMS = [(4, 3, 2, 0.02, "fp64"), (6, 2, 3, 0.005, "mixed"), (8, 1, 1, 0.1, "fp64"),
             (2, 5, 4, 0.001, "mixed"), (12, 2, 5, 0.01, "mixed"), (4, 6, 2, 0.003, "fp64"),
-            (8, 4, 3, 0.0005, "mixed"), (5, 2, 2, 0.05, "fp64")]
+            (8, 4, 3, 0.0005, "mixed"), (5, 2, 2, 0.05, "fp64"),
+            (32, 2, 3, 0.002, "mixed"), (48, 1, 2, 0.001, "fp64"), (32, 4, 2, 0.0005, "mixed")]
 
 
 def _make(R, n, k, Q, tau, prec, stream=None, **kw):
