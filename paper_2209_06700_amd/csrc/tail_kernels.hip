@@ -43,17 +43,19 @@ __device__ __forceinline__ T cheb_node(T b, T x, T xo, T ax, T rD, T ca, T cb) {
     return x + ca * (x - xo) + cb * (b - ax) * rD;
 }
 
+// The steps of one stage block's V-cycle on the tail levels: s is the block,
+// X1, X2, S, Tz the four scratch arrays (n3max values each, n3max at least the
+// node count of the largest tail level).
 template <int K, typename T>
 struct Tail {
-    const TailArgs& a;
-    int s;                          // stage block
-    T* X1;                          // scratch arrays of the largest tail level
+    int s;
+    T* X1;
     T* X2;
     T* S;
     T* Tz;
 
-    __device__ Tail(const TailArgs& args, int stage, T* scratch, long long n3max)
-        : a(args), s(stage), X1(scratch), X2(scratch + n3max), S(scratch + 2 * n3max), Tz(scratch + 3 * n3max) {}
+    __device__ Tail(int stage, T* scratch, long long n3max)
+        : s(stage), X1(scratch), X2(scratch + n3max), S(scratch + 2 * n3max), Tz(scratch + 3 * n3max) {}
 
     static __device__ __forceinline__ T dm(int i) { return diag_rt<K, 0, T>(i % K); }
     static __device__ __forceinline__ T dk(int i) { return diag_rt<K, 1, T>(i % K); }
@@ -362,7 +364,7 @@ __global__ void __launch_bounds__(kTailThreads) tail_vcycle_kernel(TailArgs a) {
     } else {
         scratch = static_cast<T*>(a.scratch) + (long long)s * a.sstride;
     }
-    Tail<K, T> t(a, s, scratch, a.n3max);
+    Tail<K, T> t(s, scratch, a.n3max);
     auto at = [&](void* base, const TailLevel& L) { return static_cast<T*>(base) + (long long)s * L.N3; };
     // down: pre-smoothing (result in `first`), residual into `second`, restriction
     for (int l = 0; l + 1 < a.nlev; ++l) {
