@@ -25,9 +25,10 @@
 //   v  = Mhat_z S + Khat_z T                                       (z)
 //
 // Work decomposition (one workgroup):
-//   * an x-y tile of TX x TY output nodes (element aligned) and a z-chunk of
-//     cz elements; all Q stages of one tile are consecutive workgroups on one
-//     XCD (shared halo reads in that XCD's L2);
+//   * an x-y tile of TX x TY output nodes (element aligned; about 32 or 64
+//     nodes wide, 8 elements tall) and a z-chunk of cz elements, both chosen
+//     per level by the autotuner; all Q stages of one tile are consecutive
+//     workgroups on one XCD (shared halo reads in that XCD's L2);
 //   * the workgroup marches up the z-chunk one node plane at a time:
 //       1. the input plane tile plus a halo of k nodes below and 1 above in x
 //          and y is staged in LDS (zero outside the interior: Dirichlet); the
@@ -35,7 +36,8 @@
 //       2. x-pass: every (row, x-element) item applies the 1D matrices to the
 //          2k+1 inputs it needs and writes k outputs to LDS;
 //       3. y-pass: every thread owns one x column and a y-pencil of k nodes
-//          (one element) and applies the 1D matrices along y from LDS;
+//          (one element; for k >= 5 two threads share a pencil, each with
+//          half of its rows) and applies the 1D matrices along y from LDS;
 //       4. z: the plane's results are accumulated element by element into k+1
 //          per-thread registers per pencil node; when an element's top plane
 //          has been added, k output planes are complete and are written (with
