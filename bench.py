@@ -128,11 +128,11 @@ def traffic_record(fetch_csv, write_csv, cz, n=64, k=4, Q=4, reps=3, ts=0):
                 "kernel_source_sha256_16": kernel_hash(), "copy_kernel": COPY_KERNEL, "copy_bytes": copy_bytes,
                 "algorithmic_bytes_per_launch": 8.0 * Q * N ** 3,
                 "commands (per chunk length CZ)": [
-                    f"rocprofv3 --pmc {c} -d gpurun_out/pmc_{c.split('_')[0].lower()}_czCZ -o op "
-                    f"--output-format csv -- python bench.py --mode op --cz CZ --tile-shape TS --op-reps {reps}"
+                    f"rocprofv3 --pmc {c} -d pmc_{c.split('_')[0].lower()}_czCZ -o op "
+                    f"--output-format csv -- python3 bench.py --mode op --cz CZ --tile-shape TS --op-reps {reps}"
                     for c in ("FETCH_SIZE", "WRITE_SIZE")]
-                + ["python bench.py --traffic-from gpurun_out/pmc_fetch_czCZ/op_counter_collection.csv "
-                   "gpurun_out/pmc_write_czCZ/op_counter_collection.csv --cz CZ --tile-shape TS"]})
+                + ["python bench.py --traffic-from pmc_fetch_czCZ/op_counter_collection.csv "
+                   "pmc_write_czCZ/op_counter_collection.csv --cz CZ --tile-shape TS"]})
     rec.pop("commands", None)
     entry = {}
     total = 0.0
