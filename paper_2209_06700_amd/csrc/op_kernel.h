@@ -26,9 +26,10 @@
 //
 // Work decomposition (one workgroup):
 //   * an x-y tile of TX x TY output nodes (element aligned; about 32 or 64
-//     nodes wide, 8 elements tall) and a z-chunk of cz elements, both chosen
-//     per level by the autotuner; all Q stages of one tile are consecutive
-//     workgroups on one XCD (shared halo reads in that XCD's L2);
+//     nodes wide, 8 elements tall, 4 for k >= 5) and a z-chunk of cz
+//     elements, both chosen per level by the autotuner; all Q stages of one
+//     tile are consecutive workgroups on one XCD (shared halo reads in that
+//     XCD's L2);
 //   * the workgroup marches up the z-chunk one node plane at a time:
 //       1. the input plane tile plus a halo of k nodes below and 1 above in x
 //          and y is staged in LDS (zero outside the interior: Dirichlet); the
@@ -85,15 +86,19 @@ struct DG {
 };
 
 // Tile shapes (TS): 0 = about 32 x-nodes, 1 = about 64 x-nodes (fp32
-// diagonal-mix kernels only), both 8 pencils tall.  The autotuner picks one
-// per level and epilogue class.
+// diagonal-mix kernels only), both 8 pencils tall (4 for k >= 5, whose
+// pencils are split).  The autotuner picks one per level and epilogue class.
 template <int K, int TS = 0>
 struct Tile {
     static constexpr int CX = ((TS == 1 ? 64 : 32) / K) > 0 ? ((TS == 1 ? 64 : 32) / K) : 1;  // elements in x
     static constexpr int TX = CX * K;                       // owned nodes in x
     // pencils per tile in y (taller tiles cut the x-pass halo rows but leave
-    // fewer resident workgroups per CU, which measured slower)
-    static constexpr int CY = 8;
+    // fewer resident workgroups per CU, which measured slower).  Split
+    // pencils (k >= 5, below) take two threads each: 4 pencils keep a
+    // workgroup at 4 waves (8 with the 64-wide tile), so that the three
+    // waves per SIMD that the fp64 kernels' registers allow hold three
+    // workgroups per CU instead of one of 8 waves.
+    static constexpr int CY = K >= 5 ? 4 : 8;
     static constexpr int TY = CY * K;                       // owned nodes in y
     // Pencil split: for k >= 5 the K rows of a y-pencil are shared by two
     // threads (rows 0..R-1 and R..K-1), which halves the per-thread
