@@ -146,16 +146,40 @@ __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
     const int gxn = cx * K + a, gyn = cy * K + b, gz0 = cz * K;
     const bool col_in = valid && gxn > 0 && gxn < N - 1 && gyn > 0 && gyn < N - 1;
     const long long colbase = (long long)gyn * N + gxn;
+    // Software pipeline over the stages: the input pencils of stage s+1 are
+    // loaded while stage s runs its passes, and the output values that the
+    // accumulation of stage s adds to are loaded when the stage starts (no
+    // other cell of this colour touches these nodes), so that neither waits
+    // for memory between two barriers.
+    auto nodal = [&](const T* base, int l) __attribute__((always_inline)) {
+        const int z = gz0 + l;
+        return (col_in && z > 0 && z < N - 1) ? base[colbase + z * NN] : T(0);
+    };
+    T nu[NQ], num[PAIR ? NQ : 1];
+#pragma unroll
+    for (int l = 0; l < NQ; ++l) {
+        nu[l] = nodal(p.u, l);
+        if constexpr (PAIR) num[l] = nodal(p.um, l);
+    }
     for (int s = 0; s < p.nstage; ++s) {
         T v[NQ], w[NQ];
         T UM[NQ];   // PAIR: the mass-term input at this z pencil of points
-        if constexpr (PAIR) {
-            const T* ums = p.um + (long long)s * p.stride;
+        T cu[NQ], vo[NQ];
+        T* vs = p.v + (long long)s * p.stride;
+#pragma unroll
+        for (int l = 0; l < NQ; ++l) {
+            cu[l] = nu[l];
+            if constexpr (PAIR) v[l] = num[l];
+            vo[l] = nodal(vs, l);
+        }
+        if (s + 1 < p.nstage) {
 #pragma unroll
             for (int l = 0; l < NQ; ++l) {
-                const int z = gz0 + l;
-                v[l] = (col_in && z > 0 && z < N - 1) ? ums[colbase + z * NN] : T(0);
+                nu[l] = nodal(p.u + (long long)(s + 1) * p.stride, l);
+                if constexpr (PAIR) num[l] = nodal(p.um + (long long)(s + 1) * p.stride, l);
             }
+        }
+        if constexpr (PAIR) {
             if (lane)
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
@@ -195,12 +219,8 @@ __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
             // A, B are free (their reads are behind the last barrier); C is
             // rewritten only after the next two barriers
         }
-        const T* us = p.u + (long long)s * p.stride;
 #pragma unroll
-        for (int l = 0; l < NQ; ++l) {
-            const int z = gz0 + l;
-            v[l] = (col_in && z > 0 && z < N - 1) ? us[colbase + z * NN] : T(0);
-        }
+        for (int l = 0; l < NQ; ++l) v[l] = cu[l];
         // values at the Gauss points: z, y, x
         if (lane)
 #pragma unroll
@@ -324,7 +344,6 @@ __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
         }
         __syncthreads();
         // back to the z nodes on z pencils, accumulated into v
-        T* vs = p.v + (long long)s * p.stride;
         if (lane) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) w[q] = C[zb + N2 * q];
@@ -334,7 +353,7 @@ __global__ void __launch_bounds__(256) deformed_op_kernel(DefArgs<T> p) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) acc = fma(T(E.gB[q][l]), w[q], acc);
                 const int z = gz0 + l;
-                if (col_in && z > 0 && z < N - 1) vs[colbase + z * NN] += acc;
+                if (col_in && z > 0 && z < N - 1) vs[colbase + z * NN] = vo[l] + acc;
             }
         }
     }
