@@ -522,9 +522,10 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--cheb-degree", type=int, default=None, help="smoother degree (library default if unset)")
     ap.add_argument("--cheb-range", type=float, default=None, help="Chebyshev range (library default if unset)")
-    ap.add_argument("--mode", choices=["full", "op", "deformed"], default="full",
+    ap.add_argument("--mode", choices=["full", "op", "deformed", "cala"], default="full",
                     help="op: only the batched fp32 block operator launches; deformed: only the "
-                         "deformed-mesh operator (both for counter runs)")
+                         "deformed-mesh operator; cala: only the fp64 stage operator A^-1 (x) M + tau I (x) K "
+                         "(all for counter runs)")
     ap.add_argument("--cz", type=int, default=None,
                     help="--mode op: fixed z-chunk length (rk_options.z_chunk); --traffic-from: the one the "
                          "counter runs used")
@@ -571,6 +572,22 @@ def main():
                           "level_ts_store": solver.info["level_ts_store"][0], "z_chunk_option": args.cz,
                           "reps": args.op_reps, "GBps": 8.0 * Q * N ** 3 / t_blk / 1e9,
                           "copy_bytes": u32.numel() * 4}), flush=True)
+        return 0
+    if args.mode == "cala":
+        # the fp64 stage operator of the Krylov method (mix pass + pair kernel)
+        # and one plain device copy of the same size, for counter runs
+        solver = R.RadauIIA(n, k, Q, tau, precision=R.RK_PREC_MIXED, mode=R.RK_BATCHED, restart=1,
+                            eig_max=[1.0] * R.n_levels(n))
+        u64 = torch.randn(Q * N ** 3, dtype=torch.float64, device="cuda")
+        v64 = torch.empty_like(u64)
+        t_cala = time_op(torch, R, solver.ctx, R.RK_OP_CALA, u64, v64, args.op_reps)
+        with torch.cuda.stream(solver.ctx.stream):
+            v64.copy_(u64)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "cala", "kernels": ["stage_mix_q_kernel<double, double, 4, false>",
+                                                      "op_kernel<4, double, 1, 0, 0>"],
+                          "cala_fp64_us": t_cala * 1e6, "krylov_cz": solver.info["krylov_cz"],
+                          "reps": args.op_reps, "copy_bytes": u64.numel() * 8}), flush=True)
         return 0
     if args.mode == "deformed":
         # the deformed-mesh operator at Q stages (fp32, eps = 0.05) and one
