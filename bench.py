@@ -437,6 +437,7 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20, autotune=1):
     t_seq, _ = run(1)
     sdofs = sum(Q * (n * k + 1) ** 3 for n, k, Q, _ in probs)
     its = [s["iterations"] for s in st]
+    ops = operator_batch_leg(torch, R, ctxs, sdofs)
     for c in ctxs:
         c.close()
     del y0
@@ -447,7 +448,53 @@ def uneven_batch(torch, R, count=64, seed=1, streams=8, restart=20, autotune=1):
             "stage_dofs": sdofs, "streams": streams, "autotune": autotune, "s_concurrent": t_conc,
             "s_sequential": t_seq,
             "speedup": t_seq / t_conc, "stage_dof_steps_per_s": sdofs / t_conc,
-            "fgmres_iterations": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
+            "fgmres_iterations": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)},
+            "operator_blocks_fp32": ops}
+
+
+def operator_batch_leg(torch, R, ctxs, sdofs, reps=20):
+    """The fp32 block operator (lam_i M + tau K on all Q stages) of every
+    problem of the uneven batch: once as one rk_apply_operator launch per
+    context (on the contexts' own streams), once as the work-list launches of
+    rk_apply_operator_batch on one stream.  Wall time per pass over the batch,
+    synchronised on both sides, after a warm-up pass."""
+    us = [torch.randn(c.Q * c.N ** 3, dtype=torch.float32, device="cuda") for c in ctxs]
+    vs = [torch.empty_like(u) for u in us]
+
+    def measure(sel):
+        def per_context():
+            for i in sel:
+                R.rk_apply_operator(ctxs[i].ctx, R.RK_OP_BLOCKS, us[i], vs[i])
+
+        def work_list():
+            R.rk_apply_operator_batch([ctxs[i].ctx for i in sel], R.RK_OP_BLOCKS, [us[i] for i in sel],
+                                      [vs[i] for i in sel])
+
+        out = {}
+        for name, fn in (("per_context_launches", per_context), ("work_list", work_list)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            out[f"{name}_ms"] = (time.perf_counter() - t0) / reps * 1e3
+        # problems of 2^23 stage-DoFs or more take their own launch, the
+        # others one work-list launch per degree and group of 12
+        alone = [i for i in sel if ctxs[i].Q * ctxs[i].N ** 3 >= 8 << 20]
+        deg = [ctxs[i].info["degree"] for i in sel if i not in alone]
+        sd = sum(ctxs[i].Q * ctxs[i].N ** 3 for i in sel)
+        out.update({"problems": len(sel), "stage_dofs": sd, "own_launches": len(alone),
+                    "list_launches": sum((deg.count(d) + 11) // 12 for d in set(deg)),
+                    "work_list_stage_dofs_per_s": sd / (out["work_list_ms"] * 1e-3),
+                    "speedup": out["per_context_launches_ms"] / out["work_list_ms"]})
+        return out
+
+    small = [i for i, c in enumerate(ctxs) if c.Q * c.N ** 3 < 1 << 20]
+    out = {"all": measure(list(range(len(ctxs)))), "below_1M_stage_dofs": measure(small)}
+    del us, vs
+    torch.cuda.empty_cache()
+    return out
 
 
 def deformed_leg(torch, R, n=64, k=4, eps=0.05, qs=(1, 2, 4, 8), reps=10):

@@ -290,6 +290,26 @@ int rk_step_batch(rk_ctx* const* ctx, int count, const double* t_n, double* cons
    deformed mesh, in fp64 only; other forms return RK_EINVAL there. */
 int rk_apply_operator(rk_ctx* ctx, int form, int dtype, const void* d_u, void* d_v);
 
+/* v_i = op_i(u_i) for count contexts at once (the uneven batch of Sec. 5.4:
+   problems of different meshes, degrees, Q and tau), for the diagonal-mix
+   forms RK_OP_BLOCKS, RK_OP_K and RK_OP_M with each context's own
+   coefficients (Sec. 3.4: all Q stage blocks of a problem in one launch).
+   d_u[i], d_v[i] are device vectors of ctx[i] as rk_apply_operator() takes
+   them, all in dtype (RK_FP64 or RK_FP32); no output may overlap an input or
+   another output.  The (tile, z-chunk, stage) items of all problems of one
+   degree go through one persistent kernel that walks them as a work list (up
+   to 12 problems per launch; one launch per degree and group of 12); a
+   problem of 2^23 stage-DoFs or more fills the GPU alone and takes its
+   context's own tuned launch instead.
+   Results equal rk_apply_operator()'s bitwise.  Asynchronous on hip_stream
+   (NULL = the default stream); the caller orders it against work queued on
+   the contexts' own streams.  Affine-mesh contexts only.  Errors (reported
+   by rk_last_error(NULL)): RK_EINVAL for count < 1, NULL arrays, contexts
+   or vectors, a deformed-mesh context, another form or dtype, overlapping
+   vectors; RK_EHIP for a failed launch. */
+int rk_apply_operator_batch(rk_ctx* const* ctx, int count, int form, int dtype, const void* const* d_u,
+                            void* const* d_v, void* hip_stream);
+
 /* x_i = one V-cycle for the block lam_i M + tau K applied to b_i, i = 1..Q,
    on [Q][N^3] vectors (RK_METHOD_COMPLEX: for the PRESB matrix H of slot i):
    the geometric multigrid of Sec. 5 (levels halve n_cells, transfer by the

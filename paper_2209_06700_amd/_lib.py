@@ -28,7 +28,7 @@ RK_STATIC_SCRATCH_BYTES = 64 << 20
 EXPORTS = ["rk_default_options", "rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info",
            "rk_step", "rk_step_batch", "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner",
            "rk_deformed_geometry_bytes", "rk_deformed_geometry", "rk_deformed_apply", "rk_last_error",
-           "rk_apply_operator_static"]
+           "rk_apply_operator_static", "rk_apply_operator_batch"]
 
 
 class rk_mesh(C.Structure):
@@ -97,11 +97,14 @@ def load():
                                       C.POINTER(C.c_double), C.c_int, vp, vp, vp, vp]
     lib.rk_apply_operator_static.argtypes = [C.POINTER(rk_mesh), C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                              vp, vp, vp]
+    lib.rk_apply_operator_batch.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.c_int, C.POINTER(vp), C.POINTER(vp),
+                                            vp]
     lib.rk_last_error.argtypes = [vp]
     lib.rk_last_error.restype = C.c_char_p
     for name in ("rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info", "rk_step", "rk_step_batch",
                  "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner", "rk_deformed_geometry_bytes",
-                 "rk_deformed_geometry", "rk_deformed_apply", "rk_apply_operator_static"):
+                 "rk_deformed_geometry", "rk_deformed_apply", "rk_apply_operator_static",
+                 "rk_apply_operator_batch"):
         getattr(lib, name).restype = C.c_int
     return lib
 

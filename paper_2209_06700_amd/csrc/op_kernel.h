@@ -212,8 +212,10 @@ struct MinWaves {
     static constexpr int v = (sizeof(T) == 4 && K <= 4 && (EPI == EPI_CHEB || EPI == EPI_CHEB1)) ? 4 : 1;
 };
 
+// One work item w < p.nwork of the operator: the x-y tile, z-chunk and
+// stage that w encodes (stage fastest, then tile x, tile y, chunk).
 template <int K, typename T, int MIX, int EPI, int TS>
-__global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) op_kernel(OpArgs<T> p) {
+__device__ __forceinline__ void op_tile(const OpArgs<T>& p, const int w) {
     using TL = Tile<K, TS>;
     constexpr int P = K + 1;
     constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, RX = TL::RX, RY = TL::RY;
@@ -230,9 +232,6 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
     __shared__ T sX1[NBUF * XSZ];
     __shared__ T sX2[NBUF * XSZ];
 
-    const int bid = blockIdx.x;
-    const int w = (bid & 7) * p.per_xcd + (bid >> 3);
-    if (w >= p.nwork) return;
     int rem = w;
     const int sl = rem % p.nstage;
     rem /= p.nstage;
@@ -802,10 +801,45 @@ __global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) o
     }
 }
 
+// One workgroup per work item; consecutive items (the Q stages of a tile)
+// go to one XCD (the hardware deals workgroups to the 8 XCDs round robin).
+template <int K, typename T, int MIX, int EPI, int TS>
+__global__ void __launch_bounds__((Tile<K, TS>::NT), (MinWaves<K, T, EPI>::v)) op_kernel(OpArgs<T> p) {
+    const int bid = blockIdx.x;
+    const int w = (bid & 7) * p.per_xcd + (bid >> 3);
+    if (w >= p.nwork) return;
+    op_tile<K, T, MIX, EPI, TS>(p, w);
+}
+
+// Work list over several problems of one degree: the items of problem i are
+// start[i] .. start[i+1]-1 of the list.  The kernel is persistent: a fixed
+// grid (a multiple of 8 workgroups) walks the list, workgroup b taking the
+// items of its XCD's contiguous range (b mod 8) in steps of grid/8, so the
+// stages and neighbouring tiles of a problem meet in one L2 as in op_kernel.
+template <typename T>
+struct OpListArgs {
+    int count, total, per_xcd;
+    int start[kOpListMax + 1];
+    OpArgs<T> e[kOpListMax];
+};
+
+template <int K, typename T>
+__global__ void __launch_bounds__((Tile<K, 0>::NT)) op_list_kernel(OpListArgs<T> a) {
+    const int b = blockIdx.x, step = gridDim.x >> 3;
+    for (int j = b >> 3; j < a.per_xcd; j += step) {
+        const int w = (b & 7) * a.per_xcd + j;
+        if (w >= a.total) break;                       // the rest of this range is past the list
+        int i = 0;
+        while (i + 1 < a.count && a.start[i + 1] <= w) ++i;
+        op_tile<K, T, MIX_DIAG, EPI_STORE, 0>(a.e[i], w - a.start[i]);
+        __syncthreads();                               // LDS is reused by the next item
+    }
+}
+
+// Fills the launch fields of p (tiles, z-chunk, work count) for tile shape TS.
 template <int K, typename T, int TS>
-hipError_t launch_op_shape(const OpLaunch& L) {
+void op_setup(const OpLaunch& L, OpArgs<T>& p) {
     using TL = Tile<K, TS>;
-    OpArgs<T> p;
     p.u = static_cast<const T*>(L.u);
     p.u2 = static_cast<const T*>(L.u2);
     p.v = static_cast<T*>(L.v);
@@ -837,6 +871,42 @@ hipError_t launch_op_shape(const OpLaunch& L) {
         p.alpha[i] = T(L.alpha[i]);
         p.beta[i] = T(L.beta[i]);
     }
+}
+
+template <int K, typename T>
+hipError_t launch_op_list_typed(const OpLaunch* L, int count, hipStream_t st) {
+    OpListArgs<T> a{};
+    a.count = count;
+    a.start[0] = 0;
+    for (int i = 0; i < count; ++i) {
+        op_setup<K, T, 0>(L[i], a.e[i]);
+        a.start[i + 1] = a.start[i] + a.e[i].nwork;
+    }
+    a.total = a.start[count];
+    a.per_xcd = (a.total + 7) / 8;
+    // persistent grid: at most kOpListGrid workgroups, a multiple of 8
+    const int grid = 8 * std::min(a.per_xcd, kOpListGrid / 8);
+    op_list_kernel<K, T><<<grid, Tile<K, 0>::NT, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// The diagonal-mix store form for the problems L[0..count) of degree K, all
+// of one dtype, in one launch (count <= kOpListMax).
+template <int K>
+hipError_t launch_op_list_k(const OpLaunch* L, int count, hipStream_t st) {
+    if (count < 1 || count > kOpListMax) return hipErrorInvalidValue;
+    for (int i = 0; i < count; ++i)
+        if (L[i].k != K || L[i].dtype != L[0].dtype || L[i].mix != MIX_DIAG || L[i].epi != EPI_STORE)
+            return hipErrorInvalidValue;
+    return L[0].dtype == RK_FP64 ? launch_op_list_typed<K, double>(L, count, st)
+                                 : launch_op_list_typed<K, float>(L, count, st);
+}
+
+template <int K, typename T, int TS>
+hipError_t launch_op_shape(const OpLaunch& L) {
+    using TL = Tile<K, TS>;
+    OpArgs<T> p;
+    op_setup<K, T, TS>(L, p);
     dim3 grid(8 * p.per_xcd), block(TL::NT);
 #define RK_OP_CASE(MX, EP)                                                      \
     if (L.mix == MX && L.epi == EP) {                                           \

@@ -3,4 +3,7 @@
 
 namespace rk {
 hipError_t launch_op_k1(const OpLaunch& L) { return dev::launch_op_k<1>(L); }
+hipError_t launch_op_list_k1(const OpLaunch* L, int count, hipStream_t st) {
+    return dev::launch_op_list_k<1>(L, count, st);
+}
 }  // namespace rk

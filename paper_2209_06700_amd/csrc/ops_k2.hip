@@ -3,4 +3,7 @@
 
 namespace rk {
 hipError_t launch_op_k2(const OpLaunch& L) { return dev::launch_op_k<2>(L); }
+hipError_t launch_op_list_k2(const OpLaunch* L, int count, hipStream_t st) {
+    return dev::launch_op_list_k<2>(L, count, st);
+}
 }  // namespace rk

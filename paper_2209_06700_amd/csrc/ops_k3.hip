@@ -3,4 +3,7 @@
 
 namespace rk {
 hipError_t launch_op_k3(const OpLaunch& L) { return dev::launch_op_k<3>(L); }
+hipError_t launch_op_list_k3(const OpLaunch* L, int count, hipStream_t st) {
+    return dev::launch_op_list_k<3>(L, count, st);
+}
 }  // namespace rk

@@ -3,4 +3,7 @@
 
 namespace rk {
 hipError_t launch_op_k4(const OpLaunch& L) { return dev::launch_op_k<4>(L); }
+hipError_t launch_op_list_k4(const OpLaunch* L, int count, hipStream_t st) {
+    return dev::launch_op_list_k<4>(L, count, st);
+}
 }  // namespace rk

@@ -40,11 +40,34 @@ hipError_t launch_op(const OpLaunch& L) {
         default: return hipErrorInvalidValue;
     }
 }
+
+hipError_t launch_op_list_k1(const OpLaunch*, int, hipStream_t);
+hipError_t launch_op_list_k2(const OpLaunch*, int, hipStream_t);
+hipError_t launch_op_list_k3(const OpLaunch*, int, hipStream_t);
+hipError_t launch_op_list_k4(const OpLaunch*, int, hipStream_t);
+hipError_t launch_op_list_k5(const OpLaunch*, int, hipStream_t);
+hipError_t launch_op_list_k6(const OpLaunch*, int, hipStream_t);
+
+hipError_t launch_op_list(const OpLaunch* L, int count, hipStream_t st) {
+    if (count < 1) return hipErrorInvalidValue;
+    switch (L[0].k) {
+        case 1: return launch_op_list_k1(L, count, st);
+        case 2: return launch_op_list_k2(L, count, st);
+        case 3: return launch_op_list_k3(L, count, st);
+        case 4: return launch_op_list_k4(L, count, st);
+        case 5: return launch_op_list_k5(L, count, st);
+        case 6: return launch_op_list_k6(L, count, st);
+        default: return hipErrorInvalidValue;
+    }
+}
 }  // namespace rk
 
 namespace {
 
 constexpr int kRedBlocks = 2048;     // blocks of the reduction kernels
+// rk_apply_operator_batch: problems of at least this many stage-DoFs per
+// launch fill the GPU alone and take their own tuned launch
+constexpr double kOpListAlone = 8.0 * (1 << 20);
 // Split V-cycles only from this many fine-level stage-DoFs per V-cycle on:
 // smaller V-cycles are latency-bound on every level, and two branches of
 // them gain nothing.
@@ -378,9 +401,9 @@ struct Timer {
 // ---------------------------------------------------------------------------
 // One operator launch.  For pair coefficients u is the mass-term input and
 // u2 the stiffness-term input.
-int op(rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, void* v,
-       const void* b, const void* xo, int n, int s0, int ns, double ca, double cb,
-       const void* u2 = nullptr, int xo_from_b = 0, double c0 = 0.0) {
+OpLaunch op_launch(const rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, void* v,
+                   const void* b, const void* xo, int n, int s0, int ns, double ca, double cb,
+                   const void* u2 = nullptr, int xo_from_b = 0, double c0 = 0.0) {
     OpLaunch L;
     L.xo_from_b = xo_from_b; L.c0 = c0;
     L.k = k; L.dtype = dtype; L.mix = cf.pair ? MIX_PAIR : MIX_DIAG; L.epi = epi;
@@ -405,6 +428,13 @@ int op(rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, vo
                 L.ts = epi == EPI_STORE ? lv.ts_st : lv.ts;
             }
     }
+    return L;
+}
+
+int op(rk_ctx* c, int k, int dtype, int epi, const Coeffs& cf, const void* u, void* v,
+       const void* b, const void* xo, int n, int s0, int ns, double ca, double cb,
+       const void* u2 = nullptr, int xo_from_b = 0, double c0 = 0.0) {
+    const OpLaunch L = op_launch(c, k, dtype, epi, cf, u, v, b, xo, n, s0, ns, ca, cb, u2, xo_from_b, c0);
     HIPCHK(c, launch_op(L));
     return RK_OK;
 }
@@ -1364,6 +1394,58 @@ int rk_apply_operator(rk_ctx* c, int form, int dtype, const void* u, void* v) {
     const void* um = cf.premix != 2 ? c->mbuf : u;
     const void* uk = cf.premix != 2 ? u : c->mbuf;
     return op(c, c->k, dtype, EPI_STORE, cf, um, v, nullptr, nullptr, c->n, 0, ns, 0, 0, uk);
+}
+
+int rk_apply_operator_batch(rk_ctx* const* ctx, int count, int form, int dtype, const void* const* u,
+                            void* const* v, void* hip_stream) {
+    if (count < 1 || !ctx || !u || !v) return fail(nullptr, RK_EINVAL, "bad batch arguments");
+    if (form != F_BLOCKS && form != F_K && form != F_M)
+        return fail(nullptr, RK_EINVAL, "batched forms: RK_OP_BLOCKS, RK_OP_K, RK_OP_M");
+    if (dtype != RK_FP64 && dtype != RK_FP32) return fail(nullptr, RK_EINVAL, "bad dtype");
+    std::vector<std::pair<const char*, const char*>> in(count), out(count);
+    for (int i = 0; i < count; ++i) {
+        if (!ctx[i] || !u[i] || !v[i]) return fail(nullptr, RK_EINVAL, "NULL context or vector in the batch");
+        if (ctx[i]->deformed) return fail(nullptr, RK_EINVAL, "the batched operator runs on affine meshes only");
+        const int ns = form == F_BLOCKS ? ctx[i]->Q : 1;
+        const size_t bytes = dsize(dtype) * (size_t)ns * ctx[i]->N3;
+        in[i] = {(const char*)u[i], (const char*)u[i] + bytes};
+        out[i] = {(const char*)v[i], (const char*)v[i] + bytes};
+    }
+    // no output may overlap any input or another output of the batch
+    auto meet = [](const std::pair<const char*, const char*>& a, const std::pair<const char*, const char*>& b) {
+        return a.first < b.second && b.first < a.second;
+    };
+    for (int i = 0; i < count; ++i)
+        for (int j = 0; j < count; ++j)
+            if (meet(out[i], in[j]) || (j < i && meet(out[i], out[j])))
+                return fail(nullptr, RK_EINVAL, "an output vector of the batch overlaps another vector");
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    // Problems that fill the GPU on their own take their context's tuned
+    // launch; the others go into one work list per degree, in chunks of at
+    // most kOpListMax problems.
+    for (int k = 1; k <= RK_MAX_DEGREE; ++k) {
+        std::vector<OpLaunch> list;
+        for (int i = 0; i < count; ++i) {
+            const rk_ctx* c = ctx[i];
+            if (c->k != k) continue;
+            const int ns = form == F_BLOCKS ? c->Q : 1;
+            OpLaunch L = op_launch(c, k, dtype, EPI_STORE, c->form[form], u[i], v[i], nullptr, nullptr, c->n, 0, ns,
+                                   0.0, 0.0);
+            if ((double)ns * c->N3 >= kOpListAlone) {
+                L.stream = st;
+                const hipError_t e = launch_op(L);
+                if (e != hipSuccess) return fail(nullptr, RK_EHIP, std::string("HIP: ") + hipGetErrorString(e));
+            } else {
+                list.push_back(L);
+            }
+        }
+        for (size_t i0 = 0; i0 < list.size(); i0 += kOpListMax) {
+            const int m = (int)std::min<size_t>(kOpListMax, list.size() - i0);
+            const hipError_t e = launch_op_list(list.data() + i0, m, st);
+            if (e != hipSuccess) return fail(nullptr, RK_EHIP, std::string("HIP: ") + hipGetErrorString(e));
+        }
+    }
+    return RK_OK;
 }
 
 int rk_vcycle(rk_ctx* c, int dtype, const void* b, void* x) {

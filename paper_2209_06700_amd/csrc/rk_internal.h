@@ -112,6 +112,14 @@ struct OpLaunch {
 };
 hipError_t launch_op(const OpLaunch& L);
 
+// Work-list launches of the operator over several problems (contexts) of one
+// degree and dtype: the diagonal-mix store form, at most kOpListMax problems
+// per launch (their launch descriptors travel in the kernel arguments), on a
+// persistent grid of at most kOpListGrid workgroups.
+constexpr int kOpListMax = 12;
+constexpr int kOpListGrid = 2048;
+hipError_t launch_op_list(const OpLaunch* L, int count, hipStream_t stream);
+
 // Records msg as the message of a failed context-free call (rk_last_error(NULL))
 // and returns code.
 int report_free_error(int code, const std::string& msg);

@@ -19,6 +19,7 @@ from ._lib import (LIB, RK_BATCHED, RK_ENOCONV, RK_FP32, RK_FP64, RK_METHOD_COMP
                    rk_options, rk_stats)
 
 __all__ = ["RKError", "rk_default_options", "rk_workspace_bytes", "rk_create", "rk_destroy", "rk_info",
+           "rk_apply_operator_batch",
            "rk_step", "rk_step_batch", "rk_apply_operator", "rk_vcycle", "rk_apply_preconditioner",
            "rk_last_error", "rk_deformed_geometry_bytes", "rk_deformed_geometry", "rk_deformed_apply",
            "rk_apply_operator_static", "RK_STATIC_SCRATCH_BYTES", "DeformedOperator",
@@ -223,6 +224,23 @@ def rk_apply_operator(ctx: Context, form: int, u: torch.Tensor, v: torch.Tensor)
     up = _vec(u, n, "u")
     vp = _vec(v, n, "v", u.dtype)
     _check(LIB.rk_apply_operator(ctx.handle, int(form), _dtype_code(u), up, vp), ctx)
+
+
+def rk_apply_operator_batch(ctxs, form: int, us, vs, stream: torch.cuda.Stream | None = None):
+    """v_i = op_i(u_i) for several contexts in work-list launches
+    (rk_apply_operator_batch; forms RK_OP_BLOCKS, RK_OP_K, RK_OP_M), on
+    `stream` (default: the current stream)."""
+    m = len(ctxs)
+    if not (len(us) == len(vs) == m) or m == 0:
+        raise ValueError("batch sequences must have one or more entries of equal length")
+    dt = us[0].dtype
+    sizes = [(1 if form in (RK_OP_K, RK_OP_M) else c.Q) * c.N ** 3 for c in ctxs]
+    handles = (C.c_void_p * m)(*[c.handle for c in ctxs])
+    uarr = (C.c_void_p * m)(*[_vec(u, n, "u", dt) for u, n in zip(us, sizes)])
+    varr = (C.c_void_p * m)(*[_vec(v, n, "v", dt) for v, n in zip(vs, sizes)])
+    st = stream if stream is not None else torch.cuda.current_stream(us[0].device)
+    _check(LIB.rk_apply_operator_batch(handles, m, int(form), _dtype_code(us[0]), uarr, varr,
+                                       C.c_void_p(st.cuda_stream)))
 
 
 def rk_vcycle(ctx: Context, b: torch.Tensor, x: torch.Tensor):

@@ -135,6 +135,23 @@ def test_step_batch_argument_checks_without_the_gpu():
     assert L.rk_step_batch(ctx, -1, t, y, None, None, None, None, 1) == _lib.RK_EINVAL
 
 
+def test_operator_batch_argument_checks_without_the_gpu():
+    """rk_apply_operator_batch rejects empty or NULL batches, NULL entries,
+    dense forms and bad dtypes before any context or vector is touched."""
+    from paper_2209_06700_amd import _lib
+    L = _lib.LIB
+    ctx = (C.c_void_p * 1)(None)
+    u = (C.c_void_p * 1)(None)
+    v = (C.c_void_p * 1)(None)
+    assert L.rk_apply_operator_batch(ctx, 0, _lib.RK_OP_BLOCKS, _lib.RK_FP32, u, v, None) == _lib.RK_EINVAL
+    assert L.rk_apply_operator_batch(None, 1, _lib.RK_OP_BLOCKS, _lib.RK_FP32, u, v, None) == _lib.RK_EINVAL
+    assert L.rk_apply_operator_batch(ctx, 1, _lib.RK_OP_BLOCKS, _lib.RK_FP32, u, v, None) == _lib.RK_EINVAL
+    assert b"NULL context" in L.rk_last_error(None)
+    for form in (_lib.RK_OP_CALA, _lib.RK_OP_STAGE, _lib.RK_OP_CBLOCKS, 6):
+        assert L.rk_apply_operator_batch(ctx, 1, form, _lib.RK_FP32, u, v, None) == _lib.RK_EINVAL
+    assert L.rk_apply_operator_batch(ctx, 1, _lib.RK_OP_K, 7, u, v, None) == _lib.RK_EINVAL
+
+
 def test_mesh_length_checked_without_the_gpu():
     """rk_mesh.length must be finite and > 0, and 1 for deformed meshes."""
     from paper_2209_06700_amd import _lib
