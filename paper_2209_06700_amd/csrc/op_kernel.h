@@ -48,6 +48,9 @@
 //   barrier; fp64 keeps single buffers (half the LDS, more resident
 //   workgroups) and two barriers.  The z-chunk re-reads the k planes of the
 //   element below it.
+// One work item is op_tile; op_kernel runs one item per workgroup for one
+// problem, op_list_kernel walks the items of several problems of one degree
+// (different meshes, Q and scales) on a persistent grid.
 #pragma once
 
 #include <hip/hip_runtime.h>
