@@ -569,10 +569,11 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--cheb-degree", type=int, default=None, help="smoother degree (library default if unset)")
     ap.add_argument("--cheb-range", type=float, default=None, help="Chebyshev range (library default if unset)")
-    ap.add_argument("--mode", choices=["full", "op", "deformed", "cala"], default="full",
+    ap.add_argument("--mode", choices=["full", "op", "deformed", "cala", "oplist"], default="full",
                     help="op: only the batched fp32 block operator launches; deformed: only the "
                          "deformed-mesh operator; cala: only the fp64 stage operator A^-1 (x) M + tau I (x) K "
-                         "(all for counter runs)")
+                         "(all for counter runs); oplist: only the uneven batch's operator leg (per-context "
+                         "and work-list launches, no steps; for kernel traces)")
     ap.add_argument("--cz", type=int, default=None,
                     help="--mode op: fixed z-chunk length (rk_options.z_chunk); --traffic-from: the one the "
                          "counter runs used")
@@ -619,6 +620,24 @@ def main():
                           "level_ts_store": solver.info["level_ts_store"][0], "z_chunk_option": args.cz,
                           "reps": args.op_reps, "GBps": 8.0 * Q * N ** 3 / t_blk / 1e9,
                           "copy_bytes": u32.numel() * 4}), flush=True)
+        return 0
+    if args.mode == "oplist":
+        import numpy as np
+        rng = np.random.default_rng(1)
+        probs = []
+        for _ in range(64):      # the draw of uneven_batch()
+            nn = int(rng.choice(BATCH_CELLS))
+            kk = int(rng.integers(1, 7))
+            QQ = int(rng.integers(1, 6))
+            probs.append((nn, kk, QQ, float(10 ** rng.uniform(-4, -1))))
+        ctxs = [R.RadauIIA(nn, kk, QQ, tt, precision=R.RK_PREC_MIXED, rtol=1e-10, restart=20, vc_streams=1)
+                for nn, kk, QQ, tt in probs]
+        torch.cuda.synchronize()
+        r = operator_batch_leg(torch, R, ctxs, sum(QQ * (nn * kk + 1) ** 3 for nn, kk, QQ, _ in probs),
+                               reps=args.op_reps)
+        for c in ctxs:
+            c.close()
+        print(json.dumps({"mode": "oplist", **r}), flush=True)
         return 0
     if args.mode == "cala":
         # the fp64 stage operator of the Krylov method (mix pass + pair kernel)
